@@ -1,0 +1,250 @@
+/*
+ * lbm.h - C ABI of the MI355X thermal lattice Boltzmann library (liblbm.so).
+ *
+ * The library runs the lattice Boltzmann update of Shim's on-lattice
+ * higher-order thermal models (the 2D 33-velocity model of Table 2 and the 3D
+ * 95-velocity model of Table 3):
+ *
+ *     f_i(x + e_i, t + 1) = (1 - omega) f_i(x, t) + omega f_i^eq(x, t)
+ *
+ * on a periodic grid (the update rule of the method; lattice units, dx = dt = 1,
+ * particle displacement e_i per step), with the 4th-order Hermite equilibrium
+ * f_i^eq = w_i rho P^(4)(v_i) (the polynomial-equilibrium form next to
+ * Formula (2), order N = m = 4 as the paragraph after Formula (8) requires),
+ * and the per-cell moments rho, U, T of the Maxwellian.  Around the update it
+ * provides initialisation from macroscopic fields, moment output, global
+ * conservation sums, checkpointed runs and a hand-written adjoint that gives
+ * gradients of a loss on the final density with respect to the initial
+ * temperature field and omega.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every function returns an lbm_status; no C++ exception crosses the ABI.
+ *    On error the call has no side effect on the context and
+ *    lbm_last_error() describes the failure.
+ *  - Grid: extents (nx, ny[, nz]), every axis periodic, N = nx*ny[*nz] cells,
+ *    linear cell index x + nx*(y + ny*z) (x fastest).
+ *  - Populations: structure of arrays, value of population i at cell c at
+ *    element i*N + c.  In LBM_FP64 each element is the double f_i.  In
+ *    LBM_FP32_SHIFTED each element is the float g_i = f_i - w_i*rho0.
+ *  - Macroscopic fields are float64 device arrays: rho[N], U[D][N]
+ *    (component-major, components x, y[, z]), T[N].  U is in cells per step,
+ *    T = k_B T / m_g in cells^2/step^2; the reference temperature is
+ *    T0 = 1/(2 c^2) (the dimensionless variables v = Theta^(-1/2) V with
+ *    Theta = 2 k_B T0 / m_g and v_i = c e_i).
+ *  - Memory: the library allocates no device memory.  Population buffers,
+ *    scratch, checkpoints, workspaces and fields are owned by the caller
+ *    (e.g. torch tensors); the library never frees them.  Device pointers
+ *    must be 256-byte aligned and stay valid while the context uses them.
+ *  - Asynchrony: kernels run on the stream given to lbm_create, in order.
+ *    Functions that return host values (lbm_conservation, lbm_adjoint's
+ *    omega gradient) synchronise that stream.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum lbm_status {
+    LBM_OK = 0,
+    LBM_E_INVALID = -1,      /* bad argument: value, size, alignment, pointer */
+    LBM_E_UNSUPPORTED = -2,  /* velocity set or precision the library has no kernel for */
+    LBM_E_DEVICE = -3,       /* a HIP runtime call or kernel launch failed */
+    LBM_E_STATE = -4,        /* call out of order (not bound / not initialised) */
+    LBM_E_NONFINITE = -5     /* a reduced diagnostic is NaN or infinite */
+} lbm_status;
+
+typedef enum lbm_precision {
+    LBM_FP64 = 0,            /* populations and arithmetic in float64 */
+    LBM_FP32_SHIFTED = 1     /* float32 deviations g_i = f_i - w_i rho0, float32 arithmetic */
+} lbm_precision;
+
+/* Largest number of velocities of a supported model. */
+#define LBM_MAX_Q 95
+
+/*
+ * lbm_velocity_set - the canonical velocity set of a supported model and its
+ * weights, solved on the host.
+ *
+ * Builds the union of the symmetry groups of Table 2 (D = 2, Q = 33) or
+ * Table 3 (D = 3, Q = 95): each group is the orbit of its representative
+ * under coordinate permutations and sign changes (the group construction
+ * before Formula (9)).  Canonical order: groups in table order, vectors of a
+ * group sorted ascending as integer tuples.  Then solves the square system of
+ * Formula (5) (even moments up to n_max = 2m = 8, Omega(4, D) equations,
+ * Formula (10) unknowns: one weight per group plus c) by Newton's method in
+ * float64, started from the printed table values.  The right-hand side is
+ * normalised so that the weights sum to one.
+ *
+ *   D, Q  : 2 and 33, or 3 and 95; otherwise LBM_E_UNSUPPORTED.
+ *   e     : host int32[Q][D] out, displacements (may be NULL).
+ *   w     : host double[Q] out, weight of each velocity (may be NULL).
+ *   c     : host double out, the speed of Formula (5) (may be NULL).
+ * Returns LBM_E_DEVICE never; LBM_E_INVALID if Newton fails to converge.
+ */
+int lbm_velocity_set(int D, int Q, int32_t* e, double* w, double* c);
+
+/*
+ * lbm_create - validate a model and a grid and make a context.
+ *
+ *   out       : receives the context (host memory owned by the library,
+ *               released by lbm_destroy).
+ *   D, Q, e   : dimension, velocity count and host int32[Q][D]
+ *               displacements; must equal a supported model in canonical
+ *               order (see lbm_velocity_set), else LBM_E_UNSUPPORTED.
+ *   w         : host double[Q] weights: positive, equal within each group,
+ *               summing to 1 within 1e-12.
+ *   c         : speed of the model; Formula (5) must hold at (w, c) with
+ *               residual <= 1e-10, else LBM_E_INVALID.
+ *   extent    : host int64[D] = {nx, ny[, nz]}, each >= 1; N*Q must fit
+ *               in int64 and nx <= 2^24.
+ *   omega     : relaxation frequency of the update rule, 0 <= omega < 2.
+ *               (omega = 0 turns the update into pure streaming.)
+ *   precision : LBM_FP64 or LBM_FP32_SHIFTED.
+ *   rho0      : shift reference density for LBM_FP32_SHIFTED (>= 0, finite;
+ *               1 for flows with mean density one); ignored for LBM_FP64.
+ *   stream    : hipStream_t on which every kernel of this context runs
+ *               (NULL = the default stream).
+ * No device call is made; the context is unbound until lbm_bind.
+ */
+int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const double* w,
+               double c, const int64_t* extent, double omega, int precision,
+               double rho0, void* stream);
+
+/*
+ * lbm_workspace_bytes - sizes of the caller-owned buffers for lbm_bind.
+ *   pop_bytes     : bytes of one population buffer (Q * N * element size).
+ *   scratch_bytes : bytes of the reduction scratch buffer.
+ */
+int lbm_workspace_bytes(const lbm_ctx* ctx, size_t* pop_bytes, size_t* scratch_bytes);
+
+/*
+ * lbm_bind - attach caller-owned device memory: two population buffers
+ * (pull streaming reads one and writes the other) and a scratch buffer of the
+ * sizes lbm_workspace_bytes reports.  Records the current HIP device.
+ * Re-binding is allowed and drops the initialised state.
+ */
+int lbm_bind(lbm_ctx* ctx, void* f_a, void* f_b, void* scratch);
+
+/*
+ * lbm_init_fields - set the populations to the equilibrium of the given
+ * fields, f_i = f_i^eq(rho, U, T) at every cell (the homogeneous initial
+ * states of the shock-tube experiment are given this way).  Computed in
+ * float64 and, for LBM_FP32_SHIFTED, rounded once to float.
+ *   rho[N], U[D][N], T[N] : device float64 inputs; rho > 0 and T > 0 are
+ *   the caller's responsibility (not checked).
+ */
+int lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* U, const double* T);
+
+/*
+ * lbm_set_populations / lbm_get_populations - copy the current populations
+ * from / to a device float64 array f[Q][N] holding f_i (not the shifted
+ * value).  For LBM_FP32_SHIFTED the setter stores float(f_i - w_i rho0).
+ */
+int lbm_set_populations(lbm_ctx* ctx, const double* f);
+int lbm_get_populations(lbm_ctx* ctx, double* f);
+
+/*
+ * lbm_step - advance n >= 0 time steps of the update rule.  Each step is one
+ * kernel: gather f_i(x - e_i) (periodic, any extent), moments, 4th-order
+ * equilibrium, BGK relaxation, coalesced store.  Asynchronous.
+ */
+int lbm_step(lbm_ctx* ctx, int n);
+
+/*
+ * lbm_moments - rho, U, T of the current populations (Formula (1) with
+ * n = 0, 1, 2): rho = sum f_i, U = sum f_i e_i / rho,
+ * T = (sum f_i |e_i|^2 / rho - |U|^2) / D.  Outputs are device float64
+ * arrays rho[N], U[D][N], T[N] (any of them may be NULL).  Asynchronous.
+ */
+int lbm_moments(lbm_ctx* ctx, double* rho, double* U, double* T);
+
+/*
+ * lbm_conservation - global sums of the conserved quantities of the current
+ * populations, reduced in float64 in a fixed order (bitwise repeatable):
+ *   out[0] = mass sum_x sum_i f_i, out[1..D] = momentum sum_x sum_i f_i e_i,
+ *   out[D+1] = energy sum_x sum_i f_i |e_i|^2 / 2.
+ *   out : host double[D+2].  Synchronises the stream.
+ * Returns LBM_E_NONFINITE (and still fills out) if any sum is not finite.
+ */
+int lbm_conservation(lbm_ctx* ctx, double* out);
+
+/* lbm_set_omega - change the relaxation frequency (0 <= omega < 2). */
+int lbm_set_omega(lbm_ctx* ctx, double omega);
+
+/*
+ * lbm_checkpoint_bytes - size of the checkpoint buffer of an n-step run with
+ * a checkpoint every k steps: ceil(n/k) population buffers.
+ */
+int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, size_t* bytes);
+
+/*
+ * lbm_run_checkpointed - like lbm_step(n), and copies the populations at
+ * t = 0, k, 2k, ... (before the step that starts each segment) into ckpt,
+ * snapshot s at byte offset s * pop_bytes.  n >= 1, k >= 1.
+ */
+int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, void* ckpt, size_t ckpt_bytes);
+
+/*
+ * lbm_adjoint_workspace_bytes - size of the workspace lbm_adjoint needs for
+ * checkpoint interval k: three population-sized buffers (adjoint ping-pong
+ * and recomputation), k steps of stored moments (D+2 values per cell per
+ * step) and the float64 reduction partials.
+ */
+int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k, size_t* bytes);
+
+/*
+ * lbm_adjoint - gradient of a loss L(rho_n) of the density after n steps
+ * with respect to the initial temperature field and omega.
+ *
+ * The forward map is f^0 = f^eq(rho_init, U_init, T_init), then n updates.
+ * The adjoint runs backwards over the segments of a checkpointed run
+ * (lbm_run_checkpointed with the same n, k, from the same initial fields):
+ * per segment it recomputes the forward steps from the checkpoint while
+ * storing the D+2 moments of each step, then applies the transposed step
+ *   lambda^t_i(x) = (1 - omega) mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2),
+ *   mu_i = lambda^{t+1}_i(x + e_i),  G_m = sum_k mu_k d f_k^eq / d m,
+ * with m = (rho, rho U, sum f |e|^2) and lambda^n_i(x) = dL/drho_n(x).
+ * Because the update is homogeneous of degree one in f, <lambda^t, f^t> is
+ * the same constant K for every t, so
+ *   dL/domega = sum_t (sum_x sum_i mu_i f_i^eq - K) / (1 - omega)
+ * needs only the stored moments; it is reduced in float64.
+ *
+ *   ckpt, ckpt_bytes   : the checkpoints of the forward run.
+ *   rho_init, U_init, T_init : device float64 initial fields of that run.
+ *   dL_drho_final      : device float64[N], dL/drho_n.
+ *   workspace, ws_bytes: device buffer of lbm_adjoint_workspace_bytes(k).
+ *   dL_dT_init         : device float64[N] out (may be NULL).
+ *   dL_domega          : host double out (may be NULL); when requested,
+ *                        |1 - omega| >= 1e-3 is required (LBM_E_INVALID
+ *                        otherwise) and the call synchronises the stream.
+ * The context's populations are left as they were.
+ */
+int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckpt_bytes,
+                const double* rho_init, const double* U_init, const double* T_init,
+                const double* dL_drho_final, void* workspace, size_t ws_bytes,
+                double* dL_dT_init, double* dL_domega);
+
+/* lbm_destroy - release the context (not the caller's device memory). */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Static description of a status code. */
+const char* lbm_status_str(int status);
+
+/* Detail of the last failure of this context ("" if none).  With ctx == NULL,
+ * the last failure of lbm_create / lbm_velocity_set on this thread. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

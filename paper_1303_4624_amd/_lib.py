@@ -1,0 +1,222 @@
+"""ctypes binding of liblbm.so with the names of the C ABI (include/lbm.h).
+
+Argument marshalling only: every computation runs in the library's HIP
+kernels.  Device buffers are passed as integer addresses (e.g.
+``tensor.data_ptr()``) and streams as ``hipStream_t`` handles
+(``torch.cuda.current_stream().cuda_stream``).  A non-zero status raises
+:class:`LBMError`.  If the library is not built the first call raises
+``RuntimeError`` -- there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liblbm.so")
+
+LBM_OK = 0
+LBM_E_INVALID = -1
+LBM_E_UNSUPPORTED = -2
+LBM_E_DEVICE = -3
+LBM_E_STATE = -4
+LBM_E_NONFINITE = -5
+LBM_FP64 = 0
+LBM_FP32_SHIFTED = 1
+LBM_MAX_Q = 95
+
+EXPORTED = [
+    "lbm_velocity_set", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
+    "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments",
+    "lbm_conservation", "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
+    "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_str",
+    "lbm_last_error",
+]
+
+
+class LBMError(RuntimeError):
+    def __init__(self, status: int, func: str, detail: str):
+        self.status = status
+        super().__init__(f"{func}: {_status_str(status)} ({status}): {detail}")
+
+
+_lib: Optional[ctypes.CDLL] = None
+_c = ctypes
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+_pd = ctypes.POINTER(ctypes.c_double)
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+_pi64 = ctypes.POINTER(ctypes.c_int64)
+_psz = ctypes.POINTER(ctypes.c_size_t)
+
+_SIGS = {
+    "lbm_velocity_set": (_c.c_int, [_c.c_int, _c.c_int, _pi32, _pd, _pd]),
+    "lbm_create": (_c.c_int, [ctypes.POINTER(_vp), _c.c_int, _c.c_int, _pi32, _pd, _c.c_double,
+                              _pi64, _c.c_double, _c.c_int, _c.c_double, _vp]),
+    "lbm_workspace_bytes": (_c.c_int, [_vp, _psz, _psz]),
+    "lbm_bind": (_c.c_int, [_vp, _vp, _vp, _vp]),
+    "lbm_init_fields": (_c.c_int, [_vp, _vp, _vp, _vp]),
+    "lbm_set_populations": (_c.c_int, [_vp, _vp]),
+    "lbm_get_populations": (_c.c_int, [_vp, _vp]),
+    "lbm_step": (_c.c_int, [_vp, _c.c_int]),
+    "lbm_moments": (_c.c_int, [_vp, _vp, _vp, _vp]),
+    "lbm_conservation": (_c.c_int, [_vp, _pd]),
+    "lbm_set_omega": (_c.c_int, [_vp, _c.c_double]),
+    "lbm_checkpoint_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _psz]),
+    "lbm_run_checkpointed": (_c.c_int, [_vp, _c.c_int, _c.c_int, _vp, _sz]),
+    "lbm_adjoint_workspace_bytes": (_c.c_int, [_vp, _c.c_int, _psz]),
+    "lbm_adjoint": (_c.c_int, [_vp, _c.c_int, _c.c_int, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _sz,
+                               _vp, _pd]),
+    "lbm_destroy": (_c.c_int, [_vp]),
+    "lbm_status_str": (_c.c_char_p, [_c.c_int]),
+    "lbm_last_error": (_c.c_char_p, [_vp]),
+}
+
+
+def library() -> ctypes.CDLL:
+    """Load liblbm.so (once); raises RuntimeError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with `python -m paper_1303_4624_amd.build` "
+                "(the HIP library is required; there is no CPU fallback)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def _status_str(status: int) -> str:
+    return library().lbm_status_str(status).decode()
+
+
+def _check(status: int, func: str, ctx=None) -> None:
+    if status != LBM_OK:
+        detail = library().lbm_last_error(ctx).decode()
+        raise LBMError(status, func, detail)
+
+
+def _addr(x) -> Optional[int]:
+    """Device address of a tensor-like (``data_ptr()``) or an int; None -> NULL."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return int(x.data_ptr())
+
+
+def lbm_status_str(status: int) -> str:
+    return _status_str(status)
+
+
+def lbm_last_error(ctx=None) -> str:
+    return library().lbm_last_error(ctx).decode()
+
+
+def lbm_velocity_set(D: int, Q: int) -> Tuple[np.ndarray, np.ndarray, float]:
+    """Canonical velocities e (Q, D) int32, weights w (Q,) and c, solved by the library."""
+    e = np.zeros((Q, D), dtype=np.int32)
+    w = np.zeros(Q, dtype=np.float64)
+    c = ctypes.c_double(0.0)
+    st = library().lbm_velocity_set(D, Q, e.ctypes.data_as(_pi32), w.ctypes.data_as(_pd),
+                                    ctypes.byref(c))
+    _check(st, "lbm_velocity_set")
+    return e, w, float(c.value)
+
+
+def lbm_create(D: int, Q: int, e, w, c: float, extent: Sequence[int], omega: float,
+               precision: int, rho0: float = 1.0, stream: int = 0) -> int:
+    e = np.ascontiguousarray(e, dtype=np.int32)
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    ext = np.ascontiguousarray(extent, dtype=np.int64)
+    if e.size != Q * D or w.size != Q or ext.size != D:
+        raise ValueError("e must be (Q, D), w (Q,), extent (D,)")
+    h = _vp()
+    st = library().lbm_create(ctypes.byref(h), D, Q, e.ctypes.data_as(_pi32),
+                              w.ctypes.data_as(_pd), float(c), ext.ctypes.data_as(_pi64),
+                              float(omega), int(precision), float(rho0), stream or None)
+    _check(st, "lbm_create")
+    return h.value
+
+
+def lbm_workspace_bytes(ctx) -> Tuple[int, int]:
+    pop, scr = _sz(0), _sz(0)
+    _check(library().lbm_workspace_bytes(ctx, ctypes.byref(pop), ctypes.byref(scr)),
+           "lbm_workspace_bytes", ctx)
+    return pop.value, scr.value
+
+
+def lbm_bind(ctx, f_a, f_b, scratch) -> None:
+    _check(library().lbm_bind(ctx, _addr(f_a), _addr(f_b), _addr(scratch)), "lbm_bind", ctx)
+
+
+def lbm_init_fields(ctx, rho, U, T) -> None:
+    _check(library().lbm_init_fields(ctx, _addr(rho), _addr(U), _addr(T)), "lbm_init_fields", ctx)
+
+
+def lbm_set_populations(ctx, f) -> None:
+    _check(library().lbm_set_populations(ctx, _addr(f)), "lbm_set_populations", ctx)
+
+
+def lbm_get_populations(ctx, f) -> None:
+    _check(library().lbm_get_populations(ctx, _addr(f)), "lbm_get_populations", ctx)
+
+
+def lbm_step(ctx, n: int) -> None:
+    _check(library().lbm_step(ctx, int(n)), "lbm_step", ctx)
+
+
+def lbm_moments(ctx, rho=None, U=None, T=None) -> None:
+    _check(library().lbm_moments(ctx, _addr(rho), _addr(U), _addr(T)), "lbm_moments", ctx)
+
+
+def lbm_conservation(ctx, D: int) -> np.ndarray:
+    out = np.zeros(D + 2, dtype=np.float64)
+    _check(library().lbm_conservation(ctx, out.ctypes.data_as(_pd)), "lbm_conservation", ctx)
+    return out
+
+
+def lbm_set_omega(ctx, omega: float) -> None:
+    _check(library().lbm_set_omega(ctx, float(omega)), "lbm_set_omega", ctx)
+
+
+def lbm_checkpoint_bytes(ctx, n: int, k: int) -> int:
+    b = _sz(0)
+    _check(library().lbm_checkpoint_bytes(ctx, int(n), int(k), ctypes.byref(b)),
+           "lbm_checkpoint_bytes", ctx)
+    return b.value
+
+
+def lbm_run_checkpointed(ctx, n: int, k: int, ckpt, ckpt_bytes: int) -> None:
+    _check(library().lbm_run_checkpointed(ctx, int(n), int(k), _addr(ckpt), int(ckpt_bytes)),
+           "lbm_run_checkpointed", ctx)
+
+
+def lbm_adjoint_workspace_bytes(ctx, k: int) -> int:
+    b = _sz(0)
+    _check(library().lbm_adjoint_workspace_bytes(ctx, int(k), ctypes.byref(b)),
+           "lbm_adjoint_workspace_bytes", ctx)
+    return b.value
+
+
+def lbm_adjoint(ctx, n: int, k: int, ckpt, ckpt_bytes: int, rho_init, U_init, T_init,
+                dL_drho_final, workspace, ws_bytes: int, dL_dT_init=None,
+                want_omega: bool = True) -> Optional[float]:
+    dw = ctypes.c_double(0.0)
+    st = library().lbm_adjoint(ctx, int(n), int(k), _addr(ckpt), int(ckpt_bytes), _addr(rho_init),
+                               _addr(U_init), _addr(T_init), _addr(dL_drho_final),
+                               _addr(workspace), int(ws_bytes), _addr(dL_dT_init),
+                               ctypes.byref(dw) if want_omega else None)
+    _check(st, "lbm_adjoint", ctx)
+    return float(dw.value) if want_omega else None
+
+
+def lbm_destroy(ctx) -> None:
+    if ctx:
+        library().lbm_destroy(ctx)

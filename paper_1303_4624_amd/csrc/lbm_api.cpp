@@ -1,0 +1,590 @@
+// lbm_api.cpp - the C ABI of liblbm (declared in include/lbm.h): context,
+// argument validation, buffer layout and the launch sequences of the update,
+// the diagnostics, checkpointed runs and the adjoint.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_host.h"
+#include "lbm_internal.h"
+
+#define LBM_API extern "C" __attribute__((visibility("default")))
+
+using lbm::KParams;
+using lbm::ModelId;
+using lbm::Prec;
+
+struct lbm_ctx {
+    ModelId model;
+    Prec prec;
+    int D = 0, Q = 0, G = 0;
+    int64_t extent[3] = {1, 1, 1};
+    long long N = 0;
+    double c = 0, T0 = 0, omega = 0, rho0 = 0;
+    double w[LBM_MAX_Q] = {};
+    double W[lbm::kMaxG] = {};
+    hipStream_t stream = nullptr;
+    int device = -1;
+    void* f[2] = {nullptr, nullptr};
+    int cur = 0;
+    void* scratch = nullptr;
+    bool bound = false;
+    bool initialized = false;
+    KParams kp{};
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+int fail(lbm_ctx* ctx, int code, const std::string& msg) {
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_err = msg;
+    return code;
+}
+
+int fail_hip(lbm_ctx* ctx, hipError_t e, const char* what) {
+    return fail(ctx, LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
+
+size_t pop_bytes(const lbm_ctx* ctx) {
+    return static_cast<size_t>(ctx->N) * ctx->Q * elem_bytes(ctx->prec);
+}
+
+size_t scratch_bytes(const lbm_ctx* ctx) {
+    const size_t parts = static_cast<size_t>(lbm::reduce_blocks(ctx->N)) * (ctx->D + 2) * 8;
+    return round_up(parts) + round_up((ctx->D + 2) * 8);
+}
+
+// Checks that [p, p + bytes) lies inside one device allocation of the
+// context's device, so that no kernel of this library can touch memory
+// outside what the caller handed over.
+int check_dev(lbm_ctx* ctx, const void* p, size_t bytes, const char* name) {
+    if (!p) return fail(ctx, LBM_E_INVALID, std::string(name) + " is NULL");
+    if (reinterpret_cast<uintptr_t>(p) % 8 != 0)
+        return fail(ctx, LBM_E_INVALID, std::string(name) + " is not 8-byte aligned");
+    hipPointerAttribute_t attr;
+    std::memset(&attr, 0, sizeof(attr));
+    hipError_t e = hipPointerGetAttributes(&attr, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, LBM_E_INVALID, std::string(name) + " is not a HIP device pointer");
+    }
+    if (attr.type != hipMemoryTypeDevice)
+        return fail(ctx, LBM_E_INVALID, std::string(name) + " is not device memory");
+    if (ctx->device >= 0 && attr.device != ctx->device)
+        return fail(ctx, LBM_E_INVALID, std::string(name) + " is on another device");
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, const_cast<void*>(p));
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, LBM_E_INVALID, std::string(name) + ": allocation range unknown");
+    }
+    const uintptr_t b = reinterpret_cast<uintptr_t>(base);
+    const uintptr_t q = reinterpret_cast<uintptr_t>(p);
+    if (q < b || q - b + bytes > size)
+        return fail(ctx, LBM_E_INVALID,
+                    std::string(name) + " is smaller than the " + std::to_string(bytes) +
+                        " bytes required");
+    return LBM_OK;
+}
+
+void fill_kparams(lbm_ctx* ctx) {
+    KParams& k = ctx->kp;
+    k.nx = static_cast<int>(ctx->extent[0]);
+    k.ny = static_cast<int>(ctx->extent[1]);
+    k.nz = ctx->D == 3 ? static_cast<int>(ctx->extent[2]) : 1;
+    k.N = ctx->N;
+    const long long rows = static_cast<long long>(k.ny) * k.nz;
+    const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, 256);
+    k.chunks = rl.chunks;
+    k.bx = rl.bx;
+    k.omega = ctx->omega;
+    k.T0 = ctx->T0;
+    k.rho0 = ctx->prec == Prec::F32S ? ctx->rho0 : 0.0;
+    for (int g = 0; g < lbm::kMaxG; ++g) {
+        k.W[g] = g < ctx->G ? ctx->W[g] : 0.0;
+        k.X[g] = g < ctx->G ? lbm::model_e2(ctx->model, g) / ctx->T0 : 0.0;
+        k.Wf[g] = static_cast<float>(k.W[g]);
+        k.Xf[g] = static_cast<float>(k.X[g]);
+    }
+    k.omegaf = static_cast<float>(k.omega);
+    k.T0f = static_cast<float>(k.T0);
+    k.invT0f = static_cast<float>(1.0 / k.T0);
+    k.rho0f = static_cast<float>(k.rho0);
+}
+
+bool omega_ok(double omega) { return std::isfinite(omega) && omega >= 0.0 && omega < 2.0; }
+
+int require_init(lbm_ctx* ctx) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (!ctx->bound) return fail(ctx, LBM_E_STATE, "no buffers bound (call lbm_bind)");
+    if (!ctx->initialized)
+        return fail(ctx, LBM_E_STATE, "populations not initialised (call lbm_init_fields)");
+    return LBM_OK;
+}
+
+int set_device(lbm_ctx* ctx) {
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipSetDevice");
+    return LBM_OK;
+}
+
+}  // namespace
+
+LBM_API const char* lbm_status_str(int status) {
+    switch (status) {
+        case LBM_OK: return "ok";
+        case LBM_E_INVALID: return "invalid argument";
+        case LBM_E_UNSUPPORTED: return "unsupported model or precision";
+        case LBM_E_DEVICE: return "HIP device error";
+        case LBM_E_STATE: return "call out of order";
+        case LBM_E_NONFINITE: return "non-finite result";
+        default: return "unknown status";
+    }
+}
+
+LBM_API const char* lbm_last_error(const lbm_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_err.c_str();
+}
+
+LBM_API int lbm_velocity_set(int D, int Q, int32_t* e, double* w, double* c) {
+    ModelId m;
+    if (!lbm::model_from_shape(D, Q, m))
+        return fail(nullptr, LBM_E_UNSUPPORTED, "only D=2,Q=33 and D=3,Q=95 are supported");
+    double W[lbm::kMaxG], cc;
+    std::string err;
+    if (!lbm::model_solve(m, W, &cc, err)) return fail(nullptr, LBM_E_INVALID, err);
+    for (int i = 0; i < Q; ++i) {
+        if (e)
+            for (int k = 0; k < D; ++k) e[i * D + k] = lbm::model_e(m, i, k);
+        if (w) w[i] = W[lbm::model_group_of(m, i)];
+    }
+    if (c) *c = cc;
+    g_err.clear();
+    return LBM_OK;
+}
+
+LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const double* w,
+                       double c, const int64_t* extent, double omega, int precision,
+                       double rho0, void* stream) {
+    if (!out) return fail(nullptr, LBM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!e || !w || !extent) return fail(nullptr, LBM_E_INVALID, "e, w and extent must be given");
+    ModelId m;
+    if (!lbm::model_from_shape(D, Q, m))
+        return fail(nullptr, LBM_E_UNSUPPORTED, "only D=2,Q=33 and D=3,Q=95 are supported");
+    if (!lbm::model_matches(m, e))
+        return fail(nullptr, LBM_E_UNSUPPORTED,
+                    "velocity list is not the canonical order of the model");
+    if (precision != LBM_FP64 && precision != LBM_FP32_SHIFTED)
+        return fail(nullptr, LBM_E_UNSUPPORTED, "precision must be LBM_FP64 or LBM_FP32_SHIFTED");
+    const int G = lbm::model_groups(m);
+    double W[lbm::kMaxG];
+    int seen[lbm::kMaxG] = {};
+    long double wsum = 0.0L;
+    for (int i = 0; i < Q; ++i) {
+        if (!std::isfinite(w[i]) || w[i] <= 0.0)
+            return fail(nullptr, LBM_E_INVALID, "weights must be finite and positive");
+        const int g = lbm::model_group_of(m, i);
+        if (!seen[g]) {
+            W[g] = w[i];
+            seen[g] = 1;
+        } else if (std::fabs(w[i] - W[g]) > 1e-14 * W[g]) {
+            return fail(nullptr, LBM_E_INVALID, "weights differ inside a symmetry group");
+        }
+        wsum += w[i];
+    }
+    if (std::fabs(static_cast<double>(wsum) - 1.0) > 1e-12)
+        return fail(nullptr, LBM_E_INVALID, "weights must sum to 1");
+    if (!std::isfinite(c) || c <= 0.0) return fail(nullptr, LBM_E_INVALID, "c must be positive");
+    const double res = lbm::model_residual(m, W, c);
+    if (!(res <= 1e-10))
+        return fail(nullptr, LBM_E_INVALID,
+                    "weights and c do not solve the moment equations (residual " +
+                        std::to_string(res) + ")");
+    long long N = 1;
+    for (int k = 0; k < D; ++k) {
+        if (extent[k] < 1) return fail(nullptr, LBM_E_INVALID, "extents must be >= 1");
+        if (extent[k] > (1LL << 24)) return fail(nullptr, LBM_E_INVALID, "extent too large");
+        N *= extent[k];
+        if (N > (1LL << 40)) return fail(nullptr, LBM_E_INVALID, "grid too large");
+    }
+    const long long rows = N / extent[0];
+    const lbm::RowLaunch rl = lbm::row_launch(static_cast<int>(extent[0]), rows, 256);
+    if (rl.blocks >= (1LL << 31) || rl.blocks * rl.bx >= (1LL << 32))
+        return fail(nullptr, LBM_E_INVALID, "grid too large for one launch");
+    if (!omega_ok(omega)) return fail(nullptr, LBM_E_INVALID, "omega must be in [0, 2)");
+    if (precision == LBM_FP32_SHIFTED && (!std::isfinite(rho0) || rho0 < 0.0))
+        return fail(nullptr, LBM_E_INVALID, "rho0 must be finite and >= 0");
+
+    lbm_ctx* ctx = new (std::nothrow) lbm_ctx();
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "out of host memory");
+    ctx->model = m;
+    ctx->prec = precision == LBM_FP64 ? Prec::F64 : Prec::F32S;
+    ctx->D = D;
+    ctx->Q = Q;
+    ctx->G = G;
+    for (int k = 0; k < D; ++k) ctx->extent[k] = extent[k];
+    ctx->N = N;
+    ctx->c = c;
+    ctx->T0 = 1.0 / (2.0 * c * c);
+    ctx->omega = omega;
+    ctx->rho0 = rho0;
+    for (int i = 0; i < Q; ++i) ctx->w[i] = w[i];
+    for (int g = 0; g < G; ++g) ctx->W[g] = W[g];
+    ctx->stream = static_cast<hipStream_t>(stream);
+    fill_kparams(ctx);
+    *out = ctx;
+    g_err.clear();
+    return LBM_OK;
+}
+
+LBM_API int lbm_workspace_bytes(const lbm_ctx* ctx, size_t* pop, size_t* scratch) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (pop) *pop = pop_bytes(ctx);
+    if (scratch) *scratch = scratch_bytes(ctx);
+    return LBM_OK;
+}
+
+LBM_API int lbm_bind(lbm_ctx* ctx, void* f_a, void* f_b, void* scratch) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipGetDevice");
+    for (void* p : {f_a, f_b, scratch}) {
+        if (p && reinterpret_cast<uintptr_t>(p) % kAlign != 0)
+            return fail(ctx, LBM_E_INVALID, "buffers must be 256-byte aligned");
+    }
+    const int saved = ctx->device;
+    ctx->device = dev;
+    int rc;
+    if ((rc = check_dev(ctx, f_a, pop_bytes(ctx), "f_a")) != LBM_OK ||
+        (rc = check_dev(ctx, f_b, pop_bytes(ctx), "f_b")) != LBM_OK ||
+        (rc = check_dev(ctx, scratch, scratch_bytes(ctx), "scratch")) != LBM_OK) {
+        ctx->device = saved;
+        return rc;
+    }
+    if (f_a == f_b) {
+        ctx->device = saved;
+        return fail(ctx, LBM_E_INVALID, "f_a and f_b must be distinct buffers");
+    }
+    ctx->f[0] = f_a;
+    ctx->f[1] = f_b;
+    ctx->cur = 0;
+    ctx->scratch = scratch;
+    ctx->bound = true;
+    ctx->initialized = false;
+    ctx->err.clear();
+    return LBM_OK;
+}
+
+LBM_API int lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* U, const double* T) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (!ctx->bound) return fail(ctx, LBM_E_STATE, "no buffers bound (call lbm_bind)");
+    int rc;
+    const size_t nb = static_cast<size_t>(ctx->N) * 8;
+    if ((rc = check_dev(ctx, rho, nb, "rho")) != LBM_OK) return rc;
+    if ((rc = check_dev(ctx, U, nb * ctx->D, "U")) != LBM_OK) return rc;
+    if ((rc = check_dev(ctx, T, nb, "T")) != LBM_OK) return rc;
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    hipError_t e = lbm::launch_init(ctx->model, ctx->prec, ctx->kp, rho, U, T, ctx->f[ctx->cur],
+                                    ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "init kernel");
+    ctx->initialized = true;
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_populations(lbm_ctx* ctx, const double* f) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (!ctx->bound) return fail(ctx, LBM_E_STATE, "no buffers bound (call lbm_bind)");
+    int rc;
+    if ((rc = check_dev(ctx, f, static_cast<size_t>(ctx->N) * ctx->Q * 8, "f")) != LBM_OK)
+        return rc;
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    hipError_t e =
+        lbm::launch_set_pop(ctx->model, ctx->prec, ctx->kp, f, ctx->f[ctx->cur], ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "set-populations kernel");
+    ctx->initialized = true;
+    return LBM_OK;
+}
+
+LBM_API int lbm_get_populations(lbm_ctx* ctx, double* f) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    if ((rc = check_dev(ctx, f, static_cast<size_t>(ctx->N) * ctx->Q * 8, "f")) != LBM_OK)
+        return rc;
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    hipError_t e =
+        lbm::launch_get_pop(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur], f, ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "get-populations kernel");
+    return LBM_OK;
+}
+
+LBM_API int lbm_step(lbm_ctx* ctx, int n) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    if (n < 0) return fail(ctx, LBM_E_INVALID, "n must be >= 0");
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    for (int t = 0; t < n; ++t) {
+        hipError_t e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
+                                        ctx->f[1 - ctx->cur], nullptr, ctx->stream);
+        if (e != hipSuccess) return fail_hip(ctx, e, "step kernel");
+        ctx->cur = 1 - ctx->cur;
+    }
+    return LBM_OK;
+}
+
+LBM_API int lbm_moments(lbm_ctx* ctx, double* rho, double* U, double* T) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    const size_t nb = static_cast<size_t>(ctx->N) * 8;
+    if (rho && (rc = check_dev(ctx, rho, nb, "rho")) != LBM_OK) return rc;
+    if (U && (rc = check_dev(ctx, U, nb * ctx->D, "U")) != LBM_OK) return rc;
+    if (T && (rc = check_dev(ctx, T, nb, "T")) != LBM_OK) return rc;
+    if (!rho && !U && !T) return LBM_OK;
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    hipError_t e = lbm::launch_moments(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur], rho, U,
+                                       T, ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "moments kernel");
+    return LBM_OK;
+}
+
+LBM_API int lbm_conservation(lbm_ctx* ctx, double* out) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    if (!out) return fail(ctx, LBM_E_INVALID, "out is NULL");
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    const int K = ctx->D + 2;
+    double* partials = static_cast<double*>(ctx->scratch);
+    const size_t parts = round_up(static_cast<size_t>(lbm::reduce_blocks(ctx->N)) * K * 8);
+    double* dres = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + parts);
+    hipError_t e = lbm::launch_conservation(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
+                                            partials, dres, ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "conservation kernels");
+    double host[5] = {0, 0, 0, 0, 0};
+    e = hipMemcpyAsync(host, dres, K * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "copy of conservation sums");
+    e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "stream synchronisation");
+    if (ctx->prec == Prec::F32S) {
+        // add the shift: sum over cells of w_i rho0 (and its moments)
+        long double m = 0, j[3] = {0, 0, 0}, en = 0;
+        for (int i = 0; i < ctx->Q; ++i) {
+            long double e2 = 0;
+            for (int k = 0; k < ctx->D; ++k) {
+                const int ek = lbm::model_e(ctx->model, i, k);
+                j[k] += static_cast<long double>(ctx->w[i]) * ek;
+                e2 += static_cast<long double>(ek) * ek;
+            }
+            m += ctx->w[i];
+            en += 0.5L * ctx->w[i] * e2;
+        }
+        const long double scale = static_cast<long double>(ctx->N) * ctx->rho0;
+        host[0] += static_cast<double>(scale * m);
+        for (int k = 0; k < ctx->D; ++k) host[1 + k] += static_cast<double>(scale * j[k]);
+        host[K - 1] += static_cast<double>(scale * en);
+    }
+    bool finite = true;
+    for (int k = 0; k < K; ++k) {
+        out[k] = host[k];
+        finite = finite && std::isfinite(host[k]);
+    }
+    if (!finite) return fail(ctx, LBM_E_NONFINITE, "a conservation sum is not finite");
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_omega(lbm_ctx* ctx, double omega) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (!omega_ok(omega)) return fail(ctx, LBM_E_INVALID, "omega must be in [0, 2)");
+    ctx->omega = omega;
+    fill_kparams(ctx);
+    return LBM_OK;
+}
+
+LBM_API int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, size_t* bytes) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (n < 1 || k < 1 || !bytes) return fail(nullptr, LBM_E_INVALID, "need n >= 1, k >= 1");
+    const size_t segs = static_cast<size_t>((n + k - 1) / k);
+    *bytes = segs * round_up(pop_bytes(ctx));
+    return LBM_OK;
+}
+
+LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, void* ckpt, size_t ckpt_bytes) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    if (n < 1 || k < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1");
+    size_t need = 0;
+    lbm_checkpoint_bytes(ctx, n, k, &need);
+    if (ckpt_bytes < need) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
+    if ((rc = check_dev(ctx, ckpt, need, "ckpt")) != LBM_OK) return rc;
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    const size_t pb = pop_bytes(ctx);
+    const size_t stride = round_up(pb);
+    const int segs = (n + k - 1) / k;
+    for (int s = 0; s < segs; ++s) {
+        hipError_t e = hipMemcpyAsync(static_cast<char*>(ckpt) + s * stride, ctx->f[ctx->cur], pb,
+                                      hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
+        const int len = std::min(k, n - s * k);
+        for (int t = 0; t < len; ++t) {
+            e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
+                                 ctx->f[1 - ctx->cur], nullptr, ctx->stream);
+            if (e != hipSuccess) return fail_hip(ctx, e, "step kernel");
+            ctx->cur = 1 - ctx->cur;
+        }
+    }
+    return LBM_OK;
+}
+
+namespace {
+
+struct AdjLayout {
+    size_t pop;       // stride of one population-sized buffer
+    size_t mom_step;  // bytes of one step of stored moments
+    size_t off_mom, off_partA, off_partK, off_out, total;
+    long long nA, nK;
+};
+
+AdjLayout adj_layout(const lbm_ctx* ctx, int k) {
+    AdjLayout L;
+    L.pop = round_up(pop_bytes(ctx));
+    L.mom_step = round_up(static_cast<size_t>(ctx->N) * (ctx->D + 2) * elem_bytes(ctx->prec));
+    L.off_mom = 3 * L.pop;
+    L.nA = lbm::step_blocks(ctx->model, ctx->prec, ctx->kp);
+    L.nK = (ctx->N + 255) / 256;
+    L.off_partA = L.off_mom + static_cast<size_t>(k) * L.mom_step;
+    L.off_partK = L.off_partA + round_up(static_cast<size_t>(L.nA) * 8);
+    L.off_out = L.off_partK + round_up(static_cast<size_t>(L.nK) * 8);
+    L.total = L.off_out + round_up(2 * 8);
+    return L;
+}
+
+}  // namespace
+
+LBM_API int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k, size_t* bytes) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (k < 1 || !bytes) return fail(nullptr, LBM_E_INVALID, "need k >= 1");
+    *bytes = adj_layout(ctx, k).total;
+    return LBM_OK;
+}
+
+LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckpt_bytes,
+                        const double* rho_init, const double* U_init, const double* T_init,
+                        const double* dL_drho_final, void* workspace, size_t ws_bytes,
+                        double* dL_dT_init, double* dL_domega) {
+    int rc;
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (!ctx->bound) return fail(ctx, LBM_E_STATE, "no buffers bound (call lbm_bind)");
+    if (n < 1 || k < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1");
+    if (dL_domega && std::fabs(1.0 - ctx->omega) < 1e-3)
+        return fail(ctx, LBM_E_INVALID,
+                    "the omega gradient needs |1 - omega| >= 1e-3 (it is divided by 1 - omega)");
+    size_t need_ck = 0;
+    lbm_checkpoint_bytes(ctx, n, k, &need_ck);
+    if (ckpt_bytes < need_ck) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
+    const AdjLayout L = adj_layout(ctx, k);
+    if (ws_bytes < L.total) return fail(ctx, LBM_E_INVALID, "adjoint workspace too small");
+    const size_t nb = static_cast<size_t>(ctx->N) * 8;
+    if ((rc = check_dev(ctx, ckpt, need_ck, "ckpt")) != LBM_OK) return rc;
+    if ((rc = check_dev(ctx, workspace, L.total, "workspace")) != LBM_OK) return rc;
+    if ((rc = check_dev(ctx, dL_drho_final, nb, "dL_drho_final")) != LBM_OK) return rc;
+    if (dL_dT_init) {
+        if ((rc = check_dev(ctx, dL_dT_init, nb, "dL_dT_init")) != LBM_OK) return rc;
+        if ((rc = check_dev(ctx, rho_init, nb, "rho_init")) != LBM_OK) return rc;
+        if ((rc = check_dev(ctx, U_init, nb * ctx->D, "U_init")) != LBM_OK) return rc;
+        if ((rc = check_dev(ctx, T_init, nb, "T_init")) != LBM_OK) return rc;
+    }
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0)
+        return fail(ctx, LBM_E_INVALID, "workspace must be 256-byte aligned");
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+
+    char* ws = static_cast<char*>(workspace);
+    void* B[3] = {ws, ws + L.pop, ws + 2 * L.pop};
+    char* mom = ws + L.off_mom;
+    double* partA = reinterpret_cast<double*>(ws + L.off_partA);
+    double* partK = reinterpret_cast<double*>(ws + L.off_partK);
+    double* dout = reinterpret_cast<double*>(ws + L.off_out);
+    const size_t pb = pop_bytes(ctx);
+    const size_t ck_stride = round_up(pb);
+    hipStream_t st = ctx->stream;
+    hipError_t e = lbm::launch_fill_zero(partA, L.nA, st);
+    if (e != hipSuccess) return fail_hip(ctx, e, "fill kernel");
+
+    const int segs = (n + k - 1) / k;
+    int lam = -1;   // index of the buffer holding the current adjoint state
+    for (int s = segs - 1; s >= 0; --s) {
+        const int t0 = s * k;
+        const int len = std::min(k, n - t0);
+        int fr[2], nf = 0;
+        for (int b = 0; b < 3 && nf < 2; ++b)
+            if (b != lam) fr[nf++] = b;
+        // recompute the segment from its checkpoint, storing the moments of
+        // every input state f^t, t = t0 .. t0 + len - 1
+        e = hipMemcpyAsync(B[fr[0]], static_cast<const char*>(ckpt) + s * ck_stride, pb,
+                           hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
+        int src = fr[0], dst = fr[1];
+        for (int j = 0; j < len; ++j) {
+            e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, B[src], B[dst],
+                                 mom + j * L.mom_step, st);
+            if (e != hipSuccess) return fail_hip(ctx, e, "recompute step kernel");
+            std::swap(src, dst);
+        }
+        if (lam < 0) {
+            // last segment: B[src] holds f^n
+            lam = 3 - fr[0] - fr[1];
+            e = lbm::launch_lambda_init(ctx->model, ctx->prec, ctx->kp, B[src], dL_drho_final,
+                                        B[lam], partK, st);
+            if (e != hipSuccess) return fail_hip(ctx, e, "adjoint initialisation kernel");
+        }
+        for (int j = len - 1; j >= 0; --j) {
+            const int nxt = (lam == fr[0]) ? fr[1] : fr[0];
+            e = lbm::launch_adjoint_step(ctx->model, ctx->prec, ctx->kp, B[lam], B[nxt],
+                                         mom + j * L.mom_step, partA, st);
+            if (e != hipSuccess) return fail_hip(ctx, e, "adjoint step kernel");
+            lam = nxt;
+        }
+    }
+    if (dL_dT_init) {
+        e = lbm::launch_dT_init(ctx->model, ctx->prec, ctx->kp, B[lam], rho_init, U_init, T_init,
+                                dL_dT_init, st);
+        if (e != hipSuccess) return fail_hip(ctx, e, "temperature gradient kernel");
+    }
+    if (dL_domega) {
+        e = lbm::launch_sum_partials(partA, L.nA, 1, 1, dout, st);
+        if (e == hipSuccess) e = lbm::launch_sum_partials(partK, L.nK, 1, 1, dout + 1, st);
+        if (e != hipSuccess) return fail_hip(ctx, e, "reduction kernel");
+        double h[2] = {0, 0};
+        e = hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return fail_hip(ctx, e, "copy of the omega gradient");
+        *dL_domega = (h[0] - static_cast<double>(n) * h[1]) / (1.0 - ctx->omega);
+        if (!std::isfinite(*dL_domega))
+            return fail(ctx, LBM_E_NONFINITE, "omega gradient is not finite");
+    }
+    return LBM_OK;
+}
+
+LBM_API int lbm_destroy(lbm_ctx* ctx) {
+    delete ctx;
+    return LBM_OK;
+}

@@ -1,0 +1,74 @@
+// lbm_internal.h - parameters and launchers shared by the C-ABI layer
+// (lbm_api.cpp) and the kernels (lbm_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "lbm_model.h"
+
+namespace lbm {
+
+enum class ModelId : int { D2Q33 = 0, D3Q95 = 1 };
+enum class Prec : int { F64 = 0, F32S = 1 };
+
+// Per-context constants, passed to every kernel by value.
+struct KParams {
+    int nx, ny, nz;           // nz = 1 in 2D
+    int chunks;               // blocks per grid row (x direction)
+    int bx;                   // threads per block (multiple of 64)
+    long long N;              // cells
+    double omega;
+    double T0;                // reference temperature 1/(2c^2)
+    double rho0;              // shift reference (FP32-shifted storage)
+    double W[kMaxG];          // group weights
+    double X[kMaxG];          // |e_g|^2 / T0
+    float omegaf, T0f, invT0f, rho0f;
+    float Wf[kMaxG];
+    float Xf[kMaxG];
+};
+
+// Launch geometry of the row-blocked kernels: one grid row (fixed y, z) is
+// split into `chunks` blocks of `bx` threads.
+struct RowLaunch {
+    int bx;
+    int chunks;
+    long long blocks;
+};
+
+RowLaunch row_launch(int nx, long long rows, int max_threads);
+
+// Number of blocks of the grid-stride reduction kernels.
+int reduce_blocks(long long N);
+constexpr int kReduceThreads = 256;
+
+// Launchers: each returns the hipError_t of the launch.
+hipError_t launch_init(ModelId m, Prec p, const KParams& kp, const double* rho, const double* U,
+                       const double* T, void* f, hipStream_t s);
+hipError_t launch_set_pop(ModelId m, Prec p, const KParams& kp, const double* fin, void* f,
+                          hipStream_t s);
+hipError_t launch_get_pop(ModelId m, Prec p, const KParams& kp, const void* f, double* fout,
+                          hipStream_t s);
+hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, void* dst,
+                       void* mom_out, hipStream_t s);
+hipError_t launch_moments(ModelId m, Prec p, const KParams& kp, const void* f, double* rho,
+                          double* U, double* T, hipStream_t s);
+hipError_t launch_conservation(ModelId m, Prec p, const KParams& kp, const void* f,
+                               double* partials, double* out, hipStream_t s);
+hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
+hipError_t launch_lambda_init(ModelId m, Prec p, const KParams& kp, const void* fn,
+                              const double* dLdrho, void* lam, double* partK, hipStream_t s);
+hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void* lam_src,
+                               void* lam_dst, const void* mom, double* partA, hipStream_t s);
+hipError_t launch_dT_init(ModelId m, Prec p, const KParams& kp, const void* lam0,
+                          const double* rho, const double* U, const double* T, double* dT,
+                          hipStream_t s);
+hipError_t launch_sum_partials(const double* part, long long n, int stride, int count,
+                               double* out, hipStream_t s);
+
+// Sizes used by the API layer for its buffers.
+long long step_blocks(ModelId m, Prec p, const KParams& kp);
+
+}  // namespace lbm

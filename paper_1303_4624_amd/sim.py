@@ -1,0 +1,139 @@
+"""Simulation: a context of liblbm with its device buffers held as torch tensors.
+
+PyTorch supplies device memory and the stream; every step of the method runs
+in the library's HIP kernels through the C ABI.
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+MODELS = {"D2Q33": (2, 33), "D3Q95": (3, 95)}
+PRECISIONS = {"fp64": L.LBM_FP64, "fp32s": L.LBM_FP32_SHIFTED}
+
+
+def _dev_bytes(nbytes: int, device) -> torch.Tensor:
+    # float64 elements keep the base 8-byte aligned; the caching allocator
+    # hands out 512-byte aligned blocks.
+    t = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=device)
+    if t.data_ptr() % 256:
+        raise RuntimeError("device allocation is not 256-byte aligned")
+    return t
+
+
+class Simulation:
+    """One periodic lattice with a supported velocity set.
+
+    model     : "D2Q33" or "D3Q95"
+    extent    : (nx, ny[, nz])
+    omega     : relaxation frequency
+    precision : "fp64" or "fp32s" (float32 deviations from w_i rho0)
+    """
+
+    def __init__(self, model: str, extent: Sequence[int], omega: float,
+                 precision: str = "fp64", rho0: float = 1.0, device="cuda",
+                 stream: Optional[torch.cuda.Stream] = None):
+        if model not in MODELS:
+            raise ValueError(f"unknown model {model}")
+        self.model = model
+        self.D, self.Q = MODELS[model]
+        self.extent = tuple(int(n) for n in extent)
+        if len(self.extent) != self.D:
+            raise ValueError("extent must have D entries")
+        self.N = int(np.prod(self.extent))
+        self.precision = precision
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.e, self.w, self.c = L.lbm_velocity_set(self.D, self.Q)
+        self.T0 = 1.0 / (2.0 * self.c * self.c)
+        self.omega = float(omega)
+        self.ctx = L.lbm_create(self.D, self.Q, self.e, self.w, self.c, self.extent, omega,
+                                PRECISIONS[precision], rho0, self.stream.cuda_stream)
+        pop, scr = L.lbm_workspace_bytes(self.ctx)
+        self.pop_bytes = pop
+        self._fa = _dev_bytes(pop, self.device)
+        self._fb = _dev_bytes(pop, self.device)
+        self._scratch = _dev_bytes(scr, self.device)
+        with torch.cuda.device(self.device):
+            L.lbm_bind(self.ctx, self._fa, self._fb, self._scratch)
+
+    # -- shapes --------------------------------------------------------
+    @property
+    def grid_shape(self) -> Tuple[int, ...]:
+        return tuple(reversed(self.extent))
+
+    def _field(self, x, comps: int = 1) -> torch.Tensor:
+        t = torch.as_tensor(x, dtype=torch.float64, device=self.device).contiguous()
+        want = (self.N * comps,)
+        if t.numel() != want[0]:
+            raise ValueError(f"field has {t.numel()} values, expected {want[0]}")
+        return t
+
+    # -- C ABI wrappers -------------------------------------------------
+    def init_fields(self, rho, U, T) -> None:
+        r, u, t = self._field(rho), self._field(U, self.D), self._field(T)
+        self._keep = (r, u, t)   # alive until the stream has consumed them
+        L.lbm_init_fields(self.ctx, r, u, t)
+
+    def set_populations(self, f) -> None:
+        t = self._field(f, self.Q)
+        self._keep = (t,)
+        L.lbm_set_populations(self.ctx, t)
+
+    def get_populations(self) -> torch.Tensor:
+        out = torch.empty((self.Q,) + self.grid_shape, dtype=torch.float64, device=self.device)
+        L.lbm_get_populations(self.ctx, out)
+        return out
+
+    def step(self, n: int = 1) -> None:
+        L.lbm_step(self.ctx, n)
+
+    def moments(self):
+        rho = torch.empty(self.grid_shape, dtype=torch.float64, device=self.device)
+        U = torch.empty((self.D,) + self.grid_shape, dtype=torch.float64, device=self.device)
+        T = torch.empty(self.grid_shape, dtype=torch.float64, device=self.device)
+        L.lbm_moments(self.ctx, rho, U, T)
+        return rho, U, T
+
+    def conservation(self) -> np.ndarray:
+        return L.lbm_conservation(self.ctx, self.D)
+
+    def set_omega(self, omega: float) -> None:
+        L.lbm_set_omega(self.ctx, omega)
+        self.omega = float(omega)
+
+    def run_checkpointed(self, n: int, k: int) -> torch.Tensor:
+        nb = L.lbm_checkpoint_bytes(self.ctx, n, k)
+        ck = _dev_bytes(nb, self.device)
+        L.lbm_run_checkpointed(self.ctx, n, k, ck, nb)
+        return ck
+
+    def adjoint(self, n: int, k: int, ckpt: torch.Tensor, rho_init, U_init, T_init,
+                dL_drho_final, want_T: bool = True, want_omega: bool = True,
+                workspace: Optional[torch.Tensor] = None):
+        """(dL/dT_init as a grid-shaped tensor or None, dL/domega or None)."""
+        wsb = L.lbm_adjoint_workspace_bytes(self.ctx, k)
+        if workspace is None or workspace.numel() * 8 < wsb:
+            workspace = _dev_bytes(wsb, self.device)
+        r, u, t = self._field(rho_init), self._field(U_init, self.D), self._field(T_init)
+        g = self._field(dL_drho_final)
+        dT = torch.empty(self.grid_shape, dtype=torch.float64, device=self.device) if want_T else None
+        dw = L.lbm_adjoint(self.ctx, n, k, ckpt, ckpt.numel() * 8, r, u, t, g, workspace, wsb,
+                           dT, want_omega)
+        self._keep = (r, u, t, g, workspace)
+        return dT, dw
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            L.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,146 @@
+"""Host-side tests of liblbm.so: it loads, exports every symbol of
+include/lbm.h, solves the model constants like the paper's tables, and
+validates arguments with the documented status codes.  No device call."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from oracle import velocity_sets as ovs
+from paper_1303_4624_amd import _lib as L
+
+MODELS = {"D2Q33": (2, 33), "D3Q95": (3, 95)}
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return L.library()
+
+
+def test_exports_every_declared_symbol(lib):
+    header = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    declared = set(re.findall(r"^\s*(?:int|const char\*)\s+(lbm_\w+)\s*\(", header, re.M))
+    assert declared == set(L.EXPORTED)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code in [0, -1, -2, -3, -4, -5]:
+        assert L.lbm_status_str(code) != "unknown status"
+    assert L.lbm_status_str(7) == "unknown status"
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_velocity_set_matches_tables_and_oracle(name):
+    D, Q = MODELS[name]
+    e, w, c = L.lbm_velocity_set(D, Q)
+    ov = ovs.velocity_set(name)
+    # same canonical order as the oracle (an interface convention)
+    assert np.array_equal(e, ov.e.astype(np.int32))
+    # printed values of Tables 2 and 3 (six significant digits)
+    table, c_printed = ovs.TABLES[name]
+    for g, (_o, _r, w_printed) in enumerate(table):
+        wg = w[ov.group == g]
+        assert np.all(wg == wg[0])
+        assert abs(wg[0] - w_printed) <= 6e-6 * w_printed
+    assert abs(c - c_printed) <= 1e-6 * c_printed
+    # both float64 Newton solutions agree
+    assert abs(c - ov.c) <= 1e-14 * c
+    assert np.max(np.abs(w - ov.w) / ov.w) < 1e-12
+    assert abs(w.sum() - 1) < 1e-14
+
+
+def test_velocity_set_unsupported():
+    with pytest.raises(L.LBMError) as ex:
+        L.lbm_velocity_set(3, 27)
+    assert ex.value.status == L.LBM_E_UNSUPPORTED
+
+
+def _args(name, **over):
+    D, Q = MODELS[name]
+    e, w, c = L.lbm_velocity_set(D, Q)
+    a = dict(D=D, Q=Q, e=e, w=w, c=c, extent=[8] * D, omega=1.2, precision=L.LBM_FP64,
+             rho0=1.0, stream=0)
+    a.update(over)
+    return a
+
+
+def _create_status(**kw):
+    try:
+        ctx = L.lbm_create(**kw)
+    except L.LBMError as ex:
+        return ex.status
+    L.lbm_destroy(ctx)
+    return L.LBM_OK
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_create_accepts_valid_arguments(name):
+    assert _create_status(**_args(name)) == L.LBM_OK
+    assert _create_status(**_args(name, precision=L.LBM_FP32_SHIFTED)) == L.LBM_OK
+    assert _create_status(**_args(name, omega=0.0)) == L.LBM_OK
+    assert _create_status(**_args(name, extent=[1] * MODELS[name][0])) == L.LBM_OK
+
+
+def test_create_rejections():
+    a = _args("D3Q95")
+    e_perm = a["e"].copy()
+    e_perm[[1, 2]] = e_perm[[2, 1]]
+    w_bad_group = a["w"].copy()
+    w_bad_group[1] *= 1.001
+    w_bad_group[2] /= 1.001
+    w_scaled = a["w"] * 1.01
+    cases = [
+        (dict(D=3, Q=27, e=a["e"][:27], w=a["w"][:27]), L.LBM_E_UNSUPPORTED),
+        (dict(e=e_perm), L.LBM_E_UNSUPPORTED),
+        (dict(precision=5), L.LBM_E_UNSUPPORTED),
+        (dict(w=w_bad_group), L.LBM_E_INVALID),
+        (dict(w=w_scaled), L.LBM_E_INVALID),
+        (dict(w=-a["w"]), L.LBM_E_INVALID),
+        (dict(c=a["c"] * 1.001), L.LBM_E_INVALID),       # weight equations fail
+        (dict(c=-1.0), L.LBM_E_INVALID),
+        (dict(extent=[8, 0, 8]), L.LBM_E_INVALID),
+        (dict(extent=[8, -3, 8]), L.LBM_E_INVALID),
+        (dict(omega=2.0), L.LBM_E_INVALID),
+        (dict(omega=-0.1), L.LBM_E_INVALID),
+        (dict(omega=float("nan")), L.LBM_E_INVALID),
+        (dict(precision=L.LBM_FP32_SHIFTED, rho0=-1.0), L.LBM_E_INVALID),
+        (dict(precision=L.LBM_FP32_SHIFTED, rho0=float("inf")), L.LBM_E_INVALID),
+    ]
+    for over, want in cases:
+        kw = dict(a)
+        kw.update(over)
+        assert _create_status(**kw) == want, over
+        assert L.lbm_last_error(None) != ""
+
+
+def test_sizes_and_state_errors():
+    kw = _args("D3Q95", extent=[16, 8, 4], precision=L.LBM_FP32_SHIFTED)
+    ctx = L.lbm_create(**kw)
+    try:
+        pop, scr = L.lbm_workspace_bytes(ctx)
+        assert pop == 95 * 16 * 8 * 4 * 4
+        assert scr > 0 and scr % 256 == 0
+        ck = L.lbm_checkpoint_bytes(ctx, 200, 20)
+        assert ck == 10 * ((pop + 255) // 256 * 256)
+        assert L.lbm_checkpoint_bytes(ctx, 21, 20) == 2 * ((pop + 255) // 256 * 256)
+        ws = L.lbm_adjoint_workspace_bytes(ctx, 20)
+        assert ws >= 3 * pop + 20 * 5 * 16 * 8 * 4 * 4
+        # unbound context: every device call is refused before touching the GPU
+        for fn, args in [(L.lbm_step, (1,)), (L.lbm_moments, (None, None, None)),
+                         (L.lbm_get_populations, (0,)), (L.lbm_init_fields, (0, 0, 0))]:
+            with pytest.raises(L.LBMError) as ex:
+                fn(ctx, *args)
+            assert ex.value.status == L.LBM_E_STATE
+        with pytest.raises(L.LBMError) as ex:
+            L.lbm_set_omega(ctx, 2.5)
+        assert ex.value.status == L.LBM_E_INVALID
+        L.lbm_set_omega(ctx, 1.7)
+        with pytest.raises(L.LBMError) as ex:
+            L.lbm_checkpoint_bytes(ctx, 0, 20)
+        assert ex.value.status == L.LBM_E_INVALID
+    finally:
+        L.lbm_destroy(ctx)

@@ -1,0 +1,173 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle on the
+same seeded inputs.  Bars: FP64 on the GPU within 1e-12 relative of the
+oracle; FP32-shifted within 1e-5 in rho, U and T after 200 steps; pure
+streaming (omega = 0) bitwise."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import gpu_run, new_sim, oracle_run, rel_errors
+from oracle import equilibrium as oeq, lbm as olbm, velocity_sets as ovs
+from synth_inputs import WORKLOADS, grid_shape, smooth_ic, workload_ic
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32S_TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.mark.parametrize("wname", ["d2q33_128x4_riemann2", "d3q95_512x4x4_riemann"])
+def test_fp64_riemann_workloads_match_oracle(wname):
+    w = WORKLOADS[wname]
+    _say("case", wname, w.extent, w.steps)
+    rho, U, th = workload_ic(w)
+    g = gpu_run(w.model, w.extent, w.omega, rho, U, th, w.steps)
+    o = oracle_run(w.model, rho, U, th, w.steps, w.omega)
+    er, eu, et = rel_errors(g, o, g[3])
+    _say("errors", er, eu, et)
+    assert er <= FP64_TOL and eu <= FP64_TOL and et <= FP64_TOL
+
+
+@pytest.mark.parametrize("model,extent,steps", [
+    ("D3Q95", (300, 5, 3), 12),     # two chunks per row, ragged tail, y/z wrap more than once
+    ("D3Q95", (1, 1, 1), 3),        # every displacement wraps onto the cell itself
+    ("D2Q33", (70, 3), 15),
+    ("D2Q33", (2, 1), 4),
+])
+def test_fp64_small_and_ragged_grids_match_oracle(model, extent, steps):
+    _say("case", model, extent, steps)
+    rho, U, th = smooth_ic(extent, seeds=(51, 52, 53, 54, 55), amp_u=0.03, amp_rho=0.05,
+                           amp_theta=0.03) if np.prod(extent) > 8 else _const_ic(extent)
+    g = gpu_run(model, extent, 1.3, rho, U, th, steps)
+    o = oracle_run(model, rho, U, th, steps, 1.3)
+    er, eu, et = rel_errors(g, o, g[3])
+    _say("errors", er, eu, et)
+    assert er <= FP64_TOL and eu <= FP64_TOL and et <= FP64_TOL
+
+
+def _const_ic(extent):
+    D = len(extent)
+    shape = grid_shape(extent)
+    rng = np.random.default_rng(9)
+    rho = 1.0 + 0.05 * rng.standard_normal(shape)
+    U = 0.03 * rng.standard_normal((D,) + shape)
+    th = 1.0 + 0.02 * rng.standard_normal(shape)
+    return rho, U, th
+
+
+@pytest.mark.parametrize("model,extent", [("D3Q95", (7, 3, 2)), ("D3Q95", (64, 4, 4)),
+                                          ("D3Q95", (260, 2, 6)), ("D2Q33", (5, 3)),
+                                          ("D2Q33", (130, 2))])
+def test_streaming_is_an_exact_permutation(model, extent):
+    # omega = 0: the update reduces to streaming; unique integer-valued
+    # populations must land exactly where the oracle's roll puts them.
+    _say("case", model, extent)
+    v = ovs.velocity_set(model)
+    shape = grid_shape(extent)
+    n = v.Q * int(np.prod(shape))
+    f0 = torch.arange(1, n + 1, dtype=torch.float64).reshape((v.Q,) + shape)
+    sim = new_sim(model, extent, 0.0)
+    sim.set_populations(f0.cuda())
+    sim.step(3)
+    got = sim.get_populations().cpu()
+    sim.close()
+    want = olbm.stream(v, olbm.stream(v, olbm.stream(v, f0)))
+    assert torch.equal(got, want)
+
+
+def test_fp32_shifted_permutation_bitwise():
+    # With rho0 = 0 the stored values are the populations themselves; integer
+    # values below 2^24 are exact in float32, so streaming must be bitwise.
+    v = ovs.velocity_set("D3Q95")
+    extent = (40, 3, 5)
+    shape = grid_shape(extent)
+    n = v.Q * int(np.prod(shape))
+    f0 = torch.arange(1, n + 1, dtype=torch.float64).reshape((v.Q,) + shape)
+    sim = new_sim("D3Q95", extent, 0.0, precision="fp32s", rho0=0.0)
+    sim.set_populations(f0.cuda())
+    sim.step(2)
+    got = sim.get_populations().cpu()
+    sim.close()
+    assert torch.equal(got, olbm.stream(v, olbm.stream(v, f0)))
+
+
+@pytest.mark.parametrize("model,extent", [("D3Q95", (40, 24, 16)), ("D2Q33", (96, 80))])
+def test_fp32_shifted_matches_fp64_oracle_after_200_steps(model, extent):
+    _say("case fp32s", model, extent)
+    rho, U, th = smooth_ic(extent, seeds=(1, 2, 3, 4, 5))
+    g = gpu_run(model, extent, 1.5, rho, U, th, 200, precision="fp32s", rho0=1.0)
+    o = oracle_run(model, rho, U, th, 200, 1.5)
+    er, eu, et = rel_errors(g, o, g[3])
+    _say("errors", er, eu, et)
+    assert er <= FP32S_TOL and eu <= FP32S_TOL and et <= FP32S_TOL
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_init_then_moments_returns_fields(precision):
+    extent = (33, 10, 7)
+    rho, U, th = smooth_ic(extent, seeds=(61, 62, 63, 64, 65), amp_u=0.04)
+    sim = new_sim("D3Q95", extent, 1.1, precision)
+    T = th * sim.T0
+    sim.init_fields(rho, U, T)
+    r, u, t = [x.cpu().numpy() for x in sim.moments()]
+    sim.close()
+    tol = 1e-14 if precision == "fp64" else 2e-7
+    assert np.max(np.abs(r - rho)) <= tol * 2
+    assert np.max(np.abs(u - U)) <= tol * 2
+    assert np.max(np.abs(t - T)) / T.max() <= tol * 4
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_populations_round_trip_and_init_matches_oracle_feq(precision):
+    extent = (20, 6, 5)
+    rho, U, th = smooth_ic(extent, seeds=(71, 72, 73, 74, 75), amp_u=0.04)
+    v = ovs.velocity_set("D3Q95")
+    sim = new_sim("D3Q95", extent, 1.1, precision)
+    sim.init_fields(rho, U, th * sim.T0)
+    f = sim.get_populations().cpu()
+    want = olbm.init_populations(v, rho, U, th * v.T0)
+    tol = 1e-15 if precision == "fp64" else 1e-8
+    assert torch.max(torch.abs(f - want)) <= tol
+    sim.set_populations(f.cuda())
+    f2 = sim.get_populations().cpu()
+    sim.close()
+    assert torch.equal(f, f2)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_conservation_sums_match_oracle_and_are_conserved(precision):
+    w = WORKLOADS["d3q95_512x4x4_riemann"]
+    v = ovs.velocity_set(w.model)
+    rho, U, th = workload_ic(w)
+    sim = new_sim(w.model, w.extent, w.omega, precision)
+    sim.init_fields(rho, U, th * sim.T0)
+    c0 = sim.conservation()
+    want = olbm.conserved(v, olbm.init_populations(v, rho, U, th * v.T0)).numpy()
+    scale = np.array([want[0], want[0], want[0], want[0], want[-1]])
+    tol = 1e-13 if precision == "fp64" else 1e-7
+    assert np.all(np.abs(c0 - want) / scale <= tol)
+    sim.step(w.steps)
+    c1 = sim.conservation()
+    c1b = sim.conservation()
+    sim.close()
+    assert np.array_equal(c1, c1b)                 # fixed-order reduction
+    drift = np.abs(c1 - c0) / scale
+    _say("drift", drift)
+    assert np.all(drift <= (1e-13 if precision == "fp64" else 1e-6))
+
+
+def test_errors_are_reported_not_faulted():
+    from paper_1303_4624_amd import _lib as L
+    sim = new_sim("D3Q95", (16, 4, 4), 1.0)
+    host = np.zeros(16 * 4 * 4)
+    with pytest.raises(L.LBMError) as ex:
+        L.lbm_init_fields(sim.ctx, host.ctypes.data, host.ctypes.data, host.ctypes.data)
+    assert ex.value.status == L.LBM_E_INVALID
+    with pytest.raises(L.LBMError) as ex:
+        L.lbm_step(sim.ctx, 1)
+    assert ex.value.status == L.LBM_E_STATE
+    sim.close()
