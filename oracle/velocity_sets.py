@@ -175,8 +175,13 @@ def solve_weights(name: str, tol: float = 1e-15, maxit: int = 60):
 
     The unknowns are the G group weights and the speed c (Formula (10):
     Omega(m, D) = 1 + number of groups).  Started from the printed table
-    values, so it converges to the root the paper reports.
+    values, so it converges to the root the paper reports.  The iteration
+    runs in float64 and is then continued at 40 decimal digits (mpmath), so
+    the returned float64 values are the rounded exact root: the Jacobian's
+    condition number (about 3e6) would otherwise leave errors near 1e-11.
     """
+    import mpmath
+
     table, c0 = TABLES[name]
     _, B, order, rhs = orbit_moment_matrix(name)
     G = len(table)
@@ -195,6 +200,24 @@ def solve_weights(name: str, tol: float = 1e-15, maxit: int = 60):
         x = x + dx
         if np.max(np.abs(dx) / np.maximum(np.abs(x), 1e-300)) < tol:
             break
+    with mpmath.workdps(40):
+        xm = [mpmath.mpf(float(v)) for v in x]
+        Bm = [[mpmath.mpf(float(b)) for b in row] for row in B]
+        rm = [mpmath.mpf(float(r)) for r in rhs]
+        for _ in range(4):
+            W, c = xm[:G], xm[G]
+            F = mpmath.matrix(G + 1, 1)
+            J = mpmath.matrix(G + 1, G + 1)
+            for k in range(G + 1):
+                o = int(order[k])
+                acc = mpmath.fsum(W[g] * Bm[k][g] for g in range(G))
+                F[k] = c ** o * acc - rm[k]
+                for g in range(G):
+                    J[k, g] = c ** o * Bm[k][g]
+                J[k, G] = (o * c ** (o - 1) if o > 0 else 0) * acc
+            dx = mpmath.lu_solve(J, -F)
+            xm = [xm[k] + dx[k] for k in range(G + 1)]
+        x = np.array([float(v) for v in xm])
     return x[:G].copy(), float(x[G])
 
 

@@ -19,6 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "liblbm.so")
 SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "lbm_model_host.cpp"]
+# Host-only sources compiled by the host C++ compiler (binary128 arithmetic).
+HOST_SOURCES = {"lbm_model_host.cpp"}
 ARCH = "gfx950"
 
 COMMON = [
@@ -36,8 +38,13 @@ def _hipcc() -> str:
 
 
 def _compile(src: str, obj: str) -> None:
-    cmd = [_hipcc(), "-x", "hip", f"--offload-arch={ARCH}", *COMMON, "-c",
-           os.path.join(CSRC, src), "-o", obj]
+    if src in HOST_SOURCES:
+        cxx = shutil.which("g++") or "g++"
+        cmd = [cxx, "-O2", "-std=c++20", "-fPIC", "-fvisibility=hidden", "-I", INCLUDE,
+               "-I", CSRC, "-c", os.path.join(CSRC, src), "-o", obj]
+    else:
+        cmd = [_hipcc(), "-x", "hip", f"--offload-arch={ARCH}", *COMMON, "-c",
+               os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     out = "\n".join(l for l in res.stdout.splitlines() if "packed-fp32-ops" not in l)
     if res.returncode != 0:
@@ -52,7 +59,8 @@ def build_library(verbose: bool = True) -> str:
     with concurrent.futures.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
         list(ex.map(lambda so: _compile(*so), zip(SOURCES, objs)))
     tmp = LIB_PATH + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-lquadmath"]
     res = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed:\n" + res.stdout)

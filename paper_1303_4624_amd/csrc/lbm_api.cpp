@@ -118,18 +118,23 @@ void fill_kparams(lbm_ctx* ctx) {
     k.chunks = rl.chunks;
     k.bx = rl.bx;
     k.omega = ctx->omega;
+    k.omc = 1.0 - ctx->omega;
+    if (ctx->prec == Prec::F32S) k.omc = static_cast<double>(static_cast<float>(k.omc));
+    k.omega_eff = 1.0 - k.omc;
     k.T0 = ctx->T0;
+    k.invT0 = 1.0 / ctx->T0;
     k.rho0 = ctx->prec == Prec::F32S ? ctx->rho0 : 0.0;
+    const double D = ctx->D;
     for (int g = 0; g < lbm::kMaxG; ++g) {
-        k.W[g] = g < ctx->G ? ctx->W[g] : 0.0;
-        k.X[g] = g < ctx->G ? lbm::model_e2(ctx->model, g) / ctx->T0 : 0.0;
-        k.Wf[g] = static_cast<float>(k.W[g]);
-        k.Xf[g] = static_cast<float>(k.X[g]);
+        const bool on = g < ctx->G;
+        const double X = on ? lbm::model_e2(ctx->model, g) / ctx->T0 : 0.0;
+        k.W[g] = on ? ctx->W[g] : 0.0;
+        k.K1[g] = 0.5 * (X - D);
+        k.K2[g] = 0.25 * (D + 2.0 - X);
+        k.K3[g] = 0.125 * (X * X - 2.0 * (D + 2.0) * X + D * (D + 2.0));
+        k.K4[g] = 0.5 * (X - D - 2.0);
+        k.K5[g] = 0.25 * (X - D - 4.0);
     }
-    k.omegaf = static_cast<float>(k.omega);
-    k.T0f = static_cast<float>(k.T0);
-    k.invT0f = static_cast<float>(1.0 / k.T0);
-    k.rho0f = static_cast<float>(k.rho0);
 }
 
 bool omega_ok(double omega) { return std::isfinite(omega) && omega >= 0.0 && omega < 2.0; }

@@ -4,7 +4,7 @@
 #include <cstdint>
 #include <string>
 
-#include "lbm_internal.h"
+#include "lbm_model.h"
 
 namespace lbm {
 

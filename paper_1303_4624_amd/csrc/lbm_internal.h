@@ -11,23 +11,25 @@
 
 namespace lbm {
 
-enum class ModelId : int { D2Q33 = 0, D3Q95 = 1 };
-enum class Prec : int { F64 = 0, F32S = 1 };
-
 // Per-context constants, passed to every kernel by value.
+//
+// The equilibrium is evaluated per symmetry group g with X_g = |e_g|^2 / T0;
+// the X-only parts of its coefficients are precomputed here:
+//   K1 = (X - D)/2, K2 = (D + 2 - X)/4, K3 = (X^2 - 2(D + 2)X + D(D + 2))/8,
+//   K4 = (X - D - 2)/2, K5 = (X - D - 4)/4.
 struct KParams {
     int nx, ny, nz;           // nz = 1 in 2D
     int chunks;               // blocks per grid row (x direction)
     int bx;                   // threads per block (multiple of 64)
     long long N;              // cells
-    double omega;
+    double omega;             // relaxation frequency
+    double omc;               // 1 - omega as used by the kernels (float-rounded for F32S)
+    double omega_eff;         // 1 - omc, so that omc + omega_eff = 1 exactly
     double T0;                // reference temperature 1/(2c^2)
+    double invT0;             // 1 / T0
     double rho0;              // shift reference (FP32-shifted storage)
     double W[kMaxG];          // group weights
-    double X[kMaxG];          // |e_g|^2 / T0
-    float omegaf, T0f, invT0f, rho0f;
-    float Wf[kMaxG];
-    float Xf[kMaxG];
+    double K1[kMaxG], K2[kMaxG], K3[kMaxG], K4[kMaxG], K5[kMaxG];
 };
 
 // Launch geometry of the row-blocked kernels: one grid row (fixed y, z) is

@@ -9,10 +9,13 @@
 //
 // Precision variants:
 //   F64  : f_i stored and computed in float64.
-//   F32S : g_i = f_i - w_i rho0 stored and computed in float32; the moments
-//          are formed from g (delta rho, j, sum g|e|^2) and the relaxation is
-//          written for g, so the O(1) part w_i rho0 never enters float32
-//          arithmetic.
+//   F32S : g_i = f_i - w_i rho0 stored in float32.  The per-velocity work
+//          (sums, polynomial, relaxation, store) is float32; the per-cell
+//          scalars (rho, U, theta) and the per-group coefficients are formed in
+//          float64 and rounded once per cell.  Rounding the model constants
+//          themselves to float32 would change the model by ~1e-8 in every cell
+//          and step alike; per-cell rounding only adds noise.  The O(1) part
+//          w_i rho0 never enters float32 arithmetic.
 //
 // Equilibrium: the 4th-order Hermite expansion of the Maxwellian, written as
 // a polynomial in s = xi_i . u_hat for each symmetry group (|e_i|^2 is
@@ -22,9 +25,9 @@
 //        + (3 u2^2 + 6 d (D + 2 - X) u2 + 3 d^2 (X^2 - 2 (D + 2) X + D (D + 2))) / 24
 //   a1 = 1 - u2/2 + d (X - D - 2)/2,   a2 = 1/2 - u2/4 + d (X - D - 4)/4
 // with xi_i = e_i / c_s, c_s^2 = T0, u_hat = U / c_s, u2 = |u_hat|^2,
-// X = |xi_i|^2 and d = T/T0 - 1.  This is the contraction of
-// sum_{n<=4} a^(n):H^(n)(xi)/n! with the Hermite coefficients of the
-// Maxwellian, collected in powers of s.
+// X = |xi_i|^2 and d = T/T0 - 1, so s = e_i . U / T0.  This is the
+// contraction of sum_{n<=4} a^(n):H^(n)(xi)/n! with the Hermite coefficients
+// of the Maxwellian, collected in powers of s.
 #include <hip/hip_runtime.h>
 
 #include <utility>
@@ -54,31 +57,6 @@ struct F32ST {
     using S = float;
     static constexpr bool shifted = true;
 };
-
-template <class R>
-__device__ __forceinline__ R kp_w(const KParams& k, int g) {
-    if constexpr (sizeof(R) == 8) return k.W[g]; else return k.Wf[g];
-}
-template <class R>
-__device__ __forceinline__ R kp_x(const KParams& k, int g) {
-    if constexpr (sizeof(R) == 8) return k.X[g]; else return k.Xf[g];
-}
-template <class R>
-__device__ __forceinline__ R kp_omega(const KParams& k) {
-    if constexpr (sizeof(R) == 8) return k.omega; else return k.omegaf;
-}
-template <class R>
-__device__ __forceinline__ R kp_T0(const KParams& k) {
-    if constexpr (sizeof(R) == 8) return k.T0; else return k.T0f;
-}
-template <class R>
-__device__ __forceinline__ R kp_invT0(const KParams& k) {
-    if constexpr (sizeof(R) == 8) return 1.0 / k.T0; else return k.invT0f;
-}
-template <class R>
-__device__ __forceinline__ R kp_rho0(const KParams& k) {
-    if constexpr (sizeof(R) == 8) return k.rho0; else return k.rho0f;
-}
 
 // (v mod n) for v in [-kMaxDisp, n - 1 + kMaxDisp]; n is wave-uniform.
 __device__ __forceinline__ int wrap_idx(int v, int n) {
@@ -138,22 +116,56 @@ __device__ __forceinline__ void gather(const S* __restrict__ src, const KParams&
     });
 }
 
-// Per-group coefficients of h = P - 1 as a polynomial in s.
-template <int D, class R>
-struct Herm {
-    R a0, a1, a2;   // h = a0 + s (a1 + s (a2 + s (1/6 + s/24)))
-    __device__ __forceinline__ void set(R X, R u2, R d) {
-        const R Dr = R(D);
-        a0 = R(0.5) * (d * (X - Dr) - u2) +
-             R(1.0 / 24.0) * (R(3) * u2 * u2 + R(6) * d * (Dr + R(2) - X) * u2 +
-                              R(3) * d * d * (X * X - R(2) * (Dr + R(2)) * X + Dr * (Dr + R(2))));
-        a1 = R(1) - R(0.5) * u2 + R(0.5) * d * (X - Dr - R(2));
-        a2 = R(0.5) - R(0.25) * u2 + R(0.25) * d * (X - Dr - R(4));
-    }
-    __device__ __forceinline__ R h(R s) const {
-        return a0 + s * (a1 + s * (a2 + s * (R(1.0 / 6.0) + s * R(1.0 / 24.0))));
-    }
+// Per-cell macroscopic values in float64 from the raw sums of the stored
+// values: m0 = sum v, j = sum v e, en = sum v |e|^2.
+struct Macro {
+    double rho, dr, ux, uy, uz, usq, d, u2;
 };
+
+template <int D, bool SHIFTED>
+__device__ __forceinline__ Macro macro_from_sums(const KParams& k, double m0, double jx, double jy,
+                                                 double jz, double en) {
+    Macro m;
+    if constexpr (SHIFTED) {
+        m.dr = m0;
+        m.rho = k.rho0 + m0;
+    } else {
+        m.rho = m0;
+        m.dr = 0.0;
+    }
+    const double inv = 1.0 / m.rho;
+    m.ux = jx * inv;
+    m.uy = jy * inv;
+    m.uz = (D == 3) ? jz * inv : 0.0;
+    m.usq = m.ux * m.ux + m.uy * m.uy + m.uz * m.uz;
+    const double invDT0 = k.invT0 * (1.0 / D);
+    if constexpr (SHIFTED) {
+        // rho D T = sum g|e|^2 + rho0 D T0 - rho |U|^2, so rho D T0 (theta - 1)
+        // = en - D T0 dr - rho |U|^2: no cancellation against rho0.
+        m.d = (en - D * k.T0 * m.dr - m.rho * m.usq) * inv * invDT0;
+    } else {
+        m.d = (en * inv - m.usq) * invDT0 - 1.0;
+    }
+    m.u2 = m.usq * k.invT0;
+    return m;
+}
+
+// Coefficients of h in powers of s for group g (float64).
+struct GCoef {
+    double a0, a1, a2;
+};
+__device__ __forceinline__ GCoef group_coef(const KParams& k, int g, double u2, double d) {
+    GCoef c;
+    c.a0 = -0.5 * u2 + 0.125 * u2 * u2 + d * (k.K1[g] + u2 * k.K2[g] + d * k.K3[g]);
+    c.a1 = 1.0 - 0.5 * u2 + d * k.K4[g];
+    c.a2 = 0.5 - 0.25 * u2 + d * k.K5[g];
+    return c;
+}
+
+template <class R>
+__device__ __forceinline__ R horner_h(R a0, R a1, R a2, R s) {
+    return a0 + s * (a1 + s * (a2 + s * (R(1.0 / 6.0) + s * R(1.0 / 24.0))));
+}
 
 // s_i = e_i . ut with compile-time integer components.
 template <int ex, int ey, int ez, class R>
@@ -198,6 +210,11 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accu
 // Forward update: pull gather, moments, equilibrium, BGK relaxation, store.
 // STORE_MOM additionally writes the D+2 moments of the input state
 // (delta rho or rho, U, theta - 1) for the adjoint.
+//
+// Relaxation: out = omc v + omega_eff W (dr + rho h)   (F32S)
+//             out = omc v + omega_eff W rho (1 + h)    (F64)
+// with omc + omega_eff = 1 exactly, so mass, momentum and energy are
+// conserved up to the rounding of each cell's own values.
 template <class M, class P, bool STORE_MOM>
 __global__ __launch_bounds__(kBlock) void k_step(const typename P::S* __restrict__ src,
                                                  typename P::S* __restrict__ dst, KParams k,
@@ -224,63 +241,40 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename P::S* __restrict
         if constexpr (ee != 0) en += R(ee) * v[i];
     });
 
-    const R T0 = kp_T0<R>(k);
-    const R invT0 = kp_invT0<R>(k);
-    const R omega = kp_omega<R>(k);
-    const R omc = R(1) - omega;
-    R rho, dr;
-    if constexpr (P::shifted) {
-        dr = m0;
-        rho = kp_rho0<R>(k) + dr;
-    } else {
-        rho = m0;
-        dr = R(0);
-    }
-    const R inv = R(1) / rho;
-    const R ux = jx * inv, uy = jy * inv, uz = (D == 3) ? jz * inv : R(0);
-    const R usq = ux * ux + uy * uy + uz * uz;
-    const R invDT0 = invT0 * R(1.0 / D);
-    R d;
-    if constexpr (P::shifted) {
-        d = (en - R(D) * T0 * dr - rho * usq) * inv * invDT0;
-    } else {
-        d = (en * inv - usq) * invDT0 - R(1);
-    }
-    const R utx = ux * invT0, uty = uy * invT0, utz = uz * invT0;
-    const R u2 = usq * invT0;
+    const Macro mc = macro_from_sums<D, P::shifted>(k, m0, jx, jy, jz, en);
+    const R utx = R(mc.ux * k.invT0), uty = R(mc.uy * k.invT0), utz = R(mc.uz * k.invT0);
+    const double wr = k.omega_eff * mc.rho;
+    const double wd = k.omega_eff * mc.dr;
+    const R omc = R(k.omc);
 
-    Herm<D, R> hc[G];
-    R ca[G], cb[G];
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        hc[g].set(kp_x<R>(k, g), u2, d);
-        const R ow = omega * kp_w<R>(k, g);
-        ca[g] = ow * rho;
-        cb[g] = ow * dr;
-    });
-
-    static_for<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int g = M::table.group[i];
-        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-        const R s = edot<ex, ey, ez>(utx, uty, utz);
-        const R h = hc[g].h(s);
-        R out;
-        if constexpr (P::shifted) {
-            out = fma(omc, v[i], fma(ca[g], h, cb[g]));
-        } else {
-            out = fma(ca[g], h, fma(omc, v[i], ca[g]));
-        }
-        if (cl.active) dst[static_cast<long long>(i) * k.N + cl.c] = out;
+        const GCoef gc = group_coef(k, g, mc.u2, mc.d);
+        const R a0 = R(gc.a0), a1 = R(gc.a1), a2 = R(gc.a2);
+        const R ca = R(wr * k.W[g]);
+        const R cb = R(wd * k.W[g]);
+        static_for<M::table.gsize[g]>([&](auto JI) {
+            constexpr int i = M::table.gstart[g] + decltype(JI)::value;
+            constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+            const R s = edot<ex, ey, ez>(utx, uty, utz);
+            const R h = horner_h(a0, a1, a2, s);
+            R out;
+            if constexpr (P::shifted) {
+                out = fma(omc, v[i], fma(ca, h, cb));
+            } else {
+                out = fma(ca, h, fma(omc, v[i], ca));
+            }
+            if (cl.active) dst[static_cast<long long>(i) * k.N + cl.c] = out;
+        });
     });
 
     if constexpr (STORE_MOM) {
         if (cl.active) {
-            mom[cl.c] = P::shifted ? dr : rho;
-            mom[k.N + cl.c] = ux;
-            mom[2 * k.N + cl.c] = uy;
-            if constexpr (D == 3) mom[3 * k.N + cl.c] = uz;
-            mom[(D + 1) * k.N + cl.c] = d;
+            mom[cl.c] = S(P::shifted ? mc.dr : mc.rho);
+            mom[k.N + cl.c] = S(mc.ux);
+            mom[2 * k.N + cl.c] = S(mc.uy);
+            if constexpr (D == 3) mom[3 * k.N + cl.c] = S(mc.uz);
+            mom[(D + 1) * k.N + cl.c] = S(mc.d);
         }
     }
 }
@@ -298,27 +292,24 @@ __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ rho,
     if (c >= k.N) return;
     const double r = rho[c];
     const double ux = U[c], uy = U[k.N + c], uz = (D == 3) ? U[2 * k.N + c] : 0.0;
-    const double invT0 = 1.0 / k.T0;
-    const double d = T[c] * invT0 - 1.0;
-    const double u2 = (ux * ux + uy * uy + uz * uz) * invT0;
-    const double utx = ux * invT0, uty = uy * invT0, utz = uz * invT0;
-    Herm<D, double> hc[G];
+    const double d = T[c] * k.invT0 - 1.0;
+    const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
+    const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        hc[g].set(k.X[g], u2, d);
-    });
-    static_for<M::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int g = M::table.group[i];
-        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-        const double h = hc[g].h(edot<ex, ey, ez>(utx, uty, utz));
+        const GCoef gc = group_coef(k, g, u2, d);
         const double w = k.W[g];
-        if constexpr (P::shifted) {
-            f[static_cast<long long>(i) * k.N + c] =
-                static_cast<float>(w * (r - k.rho0) + w * r * h);
-        } else {
-            f[static_cast<long long>(i) * k.N + c] = w * r * (1.0 + h);
-        }
+        static_for<M::table.gsize[g]>([&](auto JI) {
+            constexpr int i = M::table.gstart[g] + decltype(JI)::value;
+            constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+            const double h = horner_h(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
+            if constexpr (P::shifted) {
+                f[static_cast<long long>(i) * k.N + c] =
+                    static_cast<float>(w * (r - k.rho0) + w * r * h);
+            } else {
+                f[static_cast<long long>(i) * k.N + c] = w * r * (1.0 + h);
+            }
+        });
     });
 }
 
@@ -470,32 +461,33 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     block_sum<1>(acc, partK + blockIdx.x, false);
 }
 
-// Derivative coefficients of P = 1 + h with respect to s, u2 and d:
+// Derivative coefficients of P = 1 + h with respect to s, u2 and d, per group:
 //   P_s  = a1 + s (2 a2 + s (1/2 + s/6))
 //   P_u2 = b0 + s (-1/2 - s/4),          b0 = -1/2 + u2/4 + d (D + 2 - X)/4
 //   P_d  = c0 + s (c1 + s c2),            c0 = (X - D)/2 + (D + 2 - X) u2/4
 //                                              + d (X^2 - 2 (D + 2) X + D (D + 2))/4
 //                                         c1 = (X - D - 2)/2, c2 = (X - D - 4)/4
-template <int D, class R>
-struct HermD {
-    R a0, a1, a2, b0, c0, c1, c2;
-    __device__ __forceinline__ void set(R X, R u2, R d) {
-        const R Dr = R(D);
-        a0 = R(0.5) * (d * (X - Dr) - u2) +
-             R(1.0 / 24.0) * (R(3) * u2 * u2 + R(6) * d * (Dr + R(2) - X) * u2 +
-                              R(3) * d * d * (X * X - R(2) * (Dr + R(2)) * X + Dr * (Dr + R(2))));
-        a1 = R(1) - R(0.5) * u2 + R(0.5) * d * (X - Dr - R(2));
-        a2 = R(0.5) - R(0.25) * u2 + R(0.25) * d * (X - Dr - R(4));
-        b0 = R(-0.5) + R(0.25) * u2 + R(0.25) * d * (Dr + R(2) - X);
-        c1 = R(0.5) * (X - Dr - R(2));
-        c2 = R(0.25) * (X - Dr - R(4));
-        c0 = R(0.5) * (X - Dr) + R(0.25) * (Dr + R(2) - X) * u2 +
-             R(0.25) * d * (X * X - R(2) * (Dr + R(2)) * X + Dr * (Dr + R(2)));
-    }
+struct GDer {
+    double b0, c0, c1, c2;
 };
+__device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, double d) {
+    GDer c;
+    c.b0 = -0.5 + 0.25 * u2 + d * k.K2[g];
+    c.c0 = k.K1[g] + u2 * k.K2[g] + 2.0 * d * k.K3[g];
+    c.c1 = k.K4[g];
+    c.c2 = k.K5[g];
+    return c;
+}
 
 // One transposed step.  mu_i = lambda^{t+1}_i(x + e_i); the moments of f^t at x
-// come from the recomputation.  partA[block] += sum_x rho sum_i mu_i w_i P_i.
+// come from the recomputation.  With f^eq_i = w_i rho P_i(U, T):
+//   S0 = sum mu w P, Su = sum mu w P_u2, Sd = sum mu w P_d, Ss = sum mu w P_s e
+//   dA/dU = rho/T0 (Ss + 2 U Su), dA/dT = rho/T0 Sd     (A = sum mu f^eq)
+// and the chain rule to m = (rho, j = rho U, E = sum f |e|^2) gives
+//   G_rho = S0 - dA/dU . U / rho + dA/dT (|U|^2 - D T) / (D rho)
+//   G_j   = dA/dU / rho - 2 dA/dT U / (D rho),   G_E = dA/dT / (D rho).
+// Output lambda^t_i = omc mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2).
+// partA[block] += sum over the block's cells of A = rho S0.
 template <class M, class P>
 __global__ __launch_bounds__(kBlock) void k_adjoint(const typename P::S* __restrict__ lsrc,
                                                     typename P::S* __restrict__ ldst,
@@ -511,63 +503,67 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const typename P::S* __restr
     S mu[Q];
     gather<M, -1>(lsrc, k, cl, mu);
 
-    const R m0 = mom[cl.c];
-    const R ux = mom[k.N + cl.c];
-    const R uy = mom[2 * k.N + cl.c];
-    const R uz = (D == 3) ? mom[3 * k.N + cl.c] : R(0);
-    const R d = mom[(D + 1) * k.N + cl.c];
-    const R rho = P::shifted ? kp_rho0<R>(k) + m0 : m0;
-    const R T0 = kp_T0<R>(k);
-    const R invT0 = kp_invT0<R>(k);
-    const R omega = kp_omega<R>(k);
-    const R omc = R(1) - omega;
-    const R usq = ux * ux + uy * uy + uz * uz;
-    const R utx = ux * invT0, uty = uy * invT0, utz = uz * invT0;
-    const R u2 = usq * invT0;
-
-    HermD<D, R> hc[G];
-    static_for<G>([&](auto GI) {
-        constexpr int g = decltype(GI)::value;
-        hc[g].set(kp_x<R>(k, g), u2, d);
-    });
+    const double m0 = static_cast<double>(mom[cl.c]);
+    const double ux = static_cast<double>(mom[k.N + cl.c]);
+    const double uy = static_cast<double>(mom[2 * k.N + cl.c]);
+    const double uz = (D == 3) ? static_cast<double>(mom[3 * k.N + cl.c]) : 0.0;
+    const double d = static_cast<double>(mom[(D + 1) * k.N + cl.c]);
+    const double rho = P::shifted ? k.rho0 + m0 : m0;
+    const double usq = ux * ux + uy * uy + uz * uz;
+    const double u2 = usq * k.invT0;
+    const R utx = R(ux * k.invT0), uty = R(uy * k.invT0), utz = R(uz * k.invT0);
 
     R s0 = R(0), su2 = R(0), sd = R(0), ssx = R(0), ssy = R(0), ssz = R(0);
-    static_for<Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int g = M::table.group[i];
-        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-        const HermD<D, R>& c = hc[g];
-        const R s = edot<ex, ey, ez>(utx, uty, utz);
-        const R mw = mu[i] * kp_w<R>(k, g);
-        const R p = R(1) + c.a0 + s * (c.a1 + s * (c.a2 + s * (R(1.0 / 6.0) + s * R(1.0 / 24.0))));
-        const R ps = c.a1 + s * (R(2) * c.a2 + s * (R(0.5) + s * R(1.0 / 6.0)));
-        const R pu = c.b0 + s * (R(-0.5) - s * R(0.25));
-        const R pd = c.c0 + s * (c.c1 + s * c.c2);
-        s0 = fma(mw, p, s0);
-        su2 = fma(mw, pu, su2);
-        sd = fma(mw, pd, sd);
-        const R t = mw * ps;
-        if constexpr (ex != 0) ssx = fma(R(ex), t, ssx);
-        if constexpr (ey != 0) ssy = fma(R(ey), t, ssy);
-        if constexpr (ez != 0) ssz = fma(R(ez), t, ssz);
+    static_for<G>([&](auto GI) {
+        constexpr int g = decltype(GI)::value;
+        const GCoef gc = group_coef(k, g, u2, d);
+        const GDer gd = group_der(k, g, u2, d);
+        const R a0 = R(1.0 + gc.a0), a1 = R(gc.a1), a2 = R(gc.a2), a2x2 = R(2.0 * gc.a2);
+        const R b0 = R(gd.b0), c0 = R(gd.c0), c1 = R(gd.c1), c2 = R(gd.c2);
+        R t0 = R(0), tu = R(0), td = R(0), tx = R(0), ty = R(0), tz = R(0);
+        static_for<M::table.gsize[g]>([&](auto JI) {
+            constexpr int i = M::table.gstart[g] + decltype(JI)::value;
+            constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+            const R s = edot<ex, ey, ez>(utx, uty, utz);
+            const R p = a0 + s * (a1 + s * (a2 + s * (R(1.0 / 6.0) + s * R(1.0 / 24.0))));
+            const R ps = a1 + s * (a2x2 + s * (R(0.5) + s * R(1.0 / 6.0)));
+            const R pu = b0 + s * (R(-0.5) - s * R(0.25));
+            const R pd = c0 + s * (c1 + s * c2);
+            t0 = fma(mu[i], p, t0);
+            tu = fma(mu[i], pu, tu);
+            td = fma(mu[i], pd, td);
+            const R t = mu[i] * ps;
+            if constexpr (ex != 0) tx = fma(R(ex), t, tx);
+            if constexpr (ey != 0) ty = fma(R(ey), t, ty);
+            if constexpr (ez != 0) tz = fma(R(ez), t, tz);
+        });
+        const R wg = R(k.W[g]);
+        s0 = fma(wg, t0, s0);
+        su2 = fma(wg, tu, su2);
+        sd = fma(wg, td, sd);
+        ssx = fma(wg, tx, ssx);
+        ssy = fma(wg, ty, ssy);
+        ssz = fma(wg, tz, ssz);
     });
 
-    // Chain rule from (rho, U, T) to (rho, j = rho U, E = sum f |e|^2).
-    const R rT = rho * invT0;
-    const R aux = rT * (ssx + R(2) * ux * su2);
-    const R auy = rT * (ssy + R(2) * uy * su2);
-    const R auz = rT * (ssz + R(2) * uz * su2);
-    const R at = rT * sd;
-    const R invr = R(1) / rho;
-    const R Tm = T0 * (R(1) + d);
-    const R grho = s0 - invr * (aux * ux + auy * uy + auz * uz) +
-                   at * (usq - R(D) * Tm) * invr * R(1.0 / D);
-    const R k2 = R(2.0 / D) * at * invr;
-    const R gjx = omega * (aux * invr - k2 * ux);
-    const R gjy = omega * (auy * invr - k2 * uy);
-    const R gjz = omega * (auz * invr - k2 * uz);
-    const R ge = omega * at * invr * R(1.0 / D);
-    const R gr = omega * grho;
+    // chain rule in float64
+    const double rT = rho * k.invT0;
+    const double aux = rT * (double(ssx) + 2.0 * ux * double(su2));
+    const double auy = rT * (double(ssy) + 2.0 * uy * double(su2));
+    const double auz = rT * (double(ssz) + 2.0 * uz * double(su2));
+    const double at = rT * double(sd);
+    const double invr = 1.0 / rho;
+    const double Tm = k.T0 * (1.0 + d);
+    const double grho = double(s0) - invr * (aux * ux + auy * uy + auz * uz) +
+                        at * (usq - D * Tm) * invr * (1.0 / D);
+    const double k2 = (2.0 / D) * at * invr;
+    const double w = k.omega_eff;
+    const R gjx = R(w * (aux * invr - k2 * ux));
+    const R gjy = R(w * (auy * invr - k2 * uy));
+    const R gjz = R(w * (auz * invr - k2 * uz));
+    const R ge = R(w * at * invr * (1.0 / D));
+    const R gr = R(w * grho);
+    const R omc = R(k.omc);
 
     static_for<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -581,11 +577,12 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const typename P::S* __restr
         if (cl.active) ldst[static_cast<long long>(i) * k.N + cl.c] = fma(omc, mu[i], hv);
     });
 
-    double acc[1] = {cl.active ? static_cast<double>(rho) * static_cast<double>(s0) : 0.0};
+    double acc[1] = {cl.active ? rho * static_cast<double>(s0) : 0.0};
     block_sum<1>(acc, partA + blockIdx.x, true);
 }
 
-// dL/dT_init(x) = sum_i lambda^0_i(x) d f_i^eq / dT at the initial fields.
+// dL/dT_init(x) = sum_i lambda^0_i(x) d f_i^eq / dT at the initial fields,
+// = rho / T0 sum_i lambda_i w_i P_d,i.
 template <class M, class P>
 __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restrict__ lam,
                                                     const double* __restrict__ rho,
@@ -598,25 +595,24 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
     if (c >= k.N) return;
     const double r = rho[c];
     const double ux = U[c], uy = U[k.N + c], uz = (D == 3) ? U[2 * k.N + c] : 0.0;
-    const double invT0 = 1.0 / k.T0;
-    const double d = T[c] * invT0 - 1.0;
-    const double u2 = (ux * ux + uy * uy + uz * uz) * invT0;
-    const double utx = ux * invT0, uty = uy * invT0, utz = uz * invT0;
-    HermD<D, double> hc[G];
+    const double d = T[c] * k.invT0 - 1.0;
+    const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
+    const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
+    double sd = 0.0;
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        hc[g].set(k.X[g], u2, d);
+        const GDer gd = group_der(k, g, u2, d);
+        double tg = 0.0;
+        static_for<M::table.gsize[g]>([&](auto JI) {
+            constexpr int i = M::table.gstart[g] + decltype(JI)::value;
+            constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+            const double s = edot<ex, ey, ez>(utx, uty, utz);
+            const double pd = gd.c0 + s * (gd.c1 + s * gd.c2);
+            tg += static_cast<double>(lam[static_cast<long long>(i) * k.N + c]) * pd;
+        });
+        sd += k.W[g] * tg;
     });
-    double sd = 0.0;
-    static_for<M::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        constexpr int g = M::table.group[i];
-        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-        const double s = edot<ex, ey, ez>(utx, uty, utz);
-        const double pd = hc[g].c0 + s * (hc[g].c1 + s * hc[g].c2);
-        sd += static_cast<double>(lam[static_cast<long long>(i) * k.N + c]) * k.W[g] * pd;
-    });
-    dT[c] = r * invT0 * sd;
+    dT[c] = r * k.invT0 * sd;
 }
 
 template <class F>

@@ -14,6 +14,9 @@
 
 namespace lbm {
 
+enum class ModelId : int { D2Q33 = 0, D3Q95 = 1 };
+enum class Prec : int { F64 = 0, F32S = 1 };
+
 struct GroupRep {
     int order;      // number of velocities in the group (table column "group")
     int r[3];       // representative, unused trailing components are 0

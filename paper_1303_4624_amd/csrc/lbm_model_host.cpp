@@ -1,6 +1,12 @@
 // lbm_model_host.cpp - host-side model construction and checks: the weight
 // equations of Formula (5) and their Newton solution, used by
 // lbm_velocity_set and by the validation in lbm_create.
+//
+// Built with the host compiler (no device code).  The Newton iteration runs
+// in binary128 (__float128): the Jacobian of the weight system has a
+// condition number of about 3e6, so a float64 solve leaves errors near 1e-11
+// in the weights, a small but systematic change of the model.  In binary128
+// the result rounds to the nearest float64 of the exact root.
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -108,30 +114,6 @@ void residual_and_jacobian(const System& s, const std::vector<double>& W, double
     }
 }
 
-bool solve_dense(std::vector<std::vector<double>> A, std::vector<double> b, std::vector<double>& x) {
-    const int n = static_cast<int>(b.size());
-    for (int col = 0; col < n; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < n; ++r)
-            if (std::fabs(A[r][col]) > std::fabs(A[piv][col])) piv = r;
-        if (A[piv][col] == 0.0) return false;
-        std::swap(A[piv], A[col]);
-        std::swap(b[piv], b[col]);
-        for (int r = col + 1; r < n; ++r) {
-            const double f = A[r][col] / A[col][col];
-            for (int cc = col; cc < n; ++cc) A[r][cc] -= f * A[col][cc];
-            b[r] -= f * b[col];
-        }
-    }
-    x.assign(n, 0.0);
-    for (int r = n - 1; r >= 0; --r) {
-        double s = b[r];
-        for (int cc = r + 1; cc < n; ++cc) s -= A[r][cc] * x[cc];
-        x[r] = s / A[r][r];
-    }
-    return true;
-}
-
 }  // namespace
 
 bool model_from_shape(int D, int Q, ModelId& m) {
@@ -173,46 +155,74 @@ double model_residual(ModelId m, const double* W, double c) {
 }
 
 bool model_solve(ModelId m, double* W, double* c, std::string& err) {
+    using q = __float128;
     const ModelView v = view(m);
     const System s = build_system(m);
-    if (static_cast<int>(s.rhs.size()) != v.G + 1) {
+    const int n = static_cast<int>(s.rhs.size());
+    if (n != v.G + 1) {
         err = "weight system is not square";
         return false;
     }
-    std::vector<double> x(v.G + 1);
+    std::vector<q> x(v.G + 1);
     for (int g = 0; g < v.G; ++g) x[g] = v.printedW[g];
     x[v.G] = v.printedC;
+    auto qabs = [](q a) { return a < 0 ? -a : a; };
     bool converged = false;
-    for (int it = 0; it < 60; ++it) {
-        std::vector<double> F, dx;
-        std::vector<std::vector<double>> J;
-        std::vector<double> Wv(x.begin(), x.begin() + v.G);
-        residual_and_jacobian(s, Wv, x[v.G], F, &J);
-        for (double& f : F) f = -f;
-        if (!solve_dense(J, F, dx)) {
-            err = "singular Jacobian in the weight solve";
-            return false;
+    for (int it = 0; it < 80; ++it) {
+        // residual and Jacobian in binary128
+        std::vector<std::vector<q>> A(n, std::vector<q>(n + 1, 0));
+        for (int k = 0; k < n; ++k) {
+            q cp = 1, dcp = 0;
+            for (int p = 0; p < s.order[k]; ++p) {
+                dcp = dcp * x[v.G] + cp;
+                cp *= x[v.G];
+            }
+            q acc = 0;
+            for (int g = 0; g < v.G; ++g) {
+                acc += x[g] * static_cast<q>(s.B[k][g]);
+                A[k][g] = cp * static_cast<q>(s.B[k][g]);
+            }
+            A[k][v.G] = dcp * acc;
+            A[k][n] = -(cp * acc - static_cast<q>(s.rhs[k]));
         }
-        double rel = 0.0;
-        for (int k = 0; k <= v.G; ++k) {
+        // Gaussian elimination with partial pivoting
+        for (int col = 0; col < n; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < n; ++r)
+                if (qabs(A[r][col]) > qabs(A[piv][col])) piv = r;
+            if (A[piv][col] == 0) {
+                err = "singular Jacobian in the weight solve";
+                return false;
+            }
+            std::swap(A[piv], A[col]);
+            for (int r = col + 1; r < n; ++r) {
+                const q f = A[r][col] / A[col][col];
+                for (int cc = col; cc <= n; ++cc) A[r][cc] -= f * A[col][cc];
+            }
+        }
+        std::vector<q> dx(n, 0);
+        for (int r = n - 1; r >= 0; --r) {
+            q t = A[r][n];
+            for (int cc = r + 1; cc < n; ++cc) t -= A[r][cc] * dx[cc];
+            dx[r] = t / A[r][r];
+        }
+        q rel = 0;
+        for (int k = 0; k < n; ++k) {
             x[k] += dx[k];
-            rel = std::fmax(rel, std::fabs(dx[k]) / std::fmax(std::fabs(x[k]), 1e-300));
+            const q r = qabs(dx[k]) / qabs(x[k]);
+            if (r > rel) rel = r;
         }
-        if (rel < 1e-15) {
+        if (rel < static_cast<q>(1e-30)) {
             converged = true;
             break;
         }
     }
-    std::vector<double> Wv(x.begin(), x.begin() + v.G), F;
-    residual_and_jacobian(s, Wv, x[v.G], F, nullptr);
-    double worst = 0.0;
-    for (double f : F) worst = std::fmax(worst, std::fabs(f));
-    if (!converged && worst > 1e-13) {
+    if (!converged) {
         err = "Newton iteration for the weights did not converge";
         return false;
     }
-    for (int g = 0; g < v.G; ++g) W[g] = x[g];
-    *c = x[v.G];
+    for (int g = 0; g < v.G; ++g) W[g] = static_cast<double>(x[g]);
+    *c = static_cast<double>(x[v.G]);
     return true;
 }
 
