@@ -25,8 +25,14 @@
  *  - Grid: extents (nx, ny[, nz]), every axis periodic, N = nx*ny[*nz] cells,
  *    linear cell index x + nx*(y + ny*z) (x fastest).
  *  - Populations: structure of arrays, value of population i at cell c at
- *    element i*N + c.  In LBM_FP64 each element is the double f_i.  In
- *    LBM_FP32_SHIFTED each element is the float g_i = f_i - w_i*rho0.
+ *    element i*N + c.  In LBM_FP64 each element is the double f*_i.  In
+ *    LBM_FP32_SHIFTED each element is the float g_i = f*_i - w_i*rho0.
+ *  - Stored state: the post-collision populations
+ *    f*_i(x, t) = (1 - omega) f_i(x, t) + omega f_i^eq(x, t), i.e. the
+ *    right-hand side of the update rule; the next step moves them to x + e_i,
+ *    f_i(x + e_i, t + 1) = f*_i(x, t).  Collision conserves rho, rho U and
+ *    sum f |e|^2, so the moments of f* are those of f at time t.  After
+ *    lbm_init_fields, f* = f = f^eq.
  *  - Macroscopic fields are float64 device arrays: rho[N], U[D][N]
  *    (component-major, components x, y[, z]), T[N].  U is in cells per step,
  *    T = k_B T / m_g in cells^2/step^2; the reference temperature is
@@ -81,8 +87,8 @@ typedef enum lbm_precision {
  * group sorted ascending as integer tuples.  Then solves the square system of
  * Formula (5) (even moments up to n_max = 2m = 8, Omega(4, D) equations,
  * Formula (10) unknowns: one weight per group plus c) by Newton's method in
- * float64, started from the printed table values.  The right-hand side is
- * normalised so that the weights sum to one.
+ * binary128, started from the printed table values, and rounds the root to
+ * float64.  The right-hand side is normalised so that the weights sum to one.
  *
  *   D, Q  : 2 and 33, or 3 and 95; otherwise LBM_E_UNSUPPORTED.
  *   e     : host int32[Q][D] out, displacements (may be NULL).
@@ -145,17 +151,19 @@ int lbm_bind(lbm_ctx* ctx, void* f_a, void* f_b, void* scratch);
 int lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* U, const double* T);
 
 /*
- * lbm_set_populations / lbm_get_populations - copy the current populations
- * from / to a device float64 array f[Q][N] holding f_i (not the shifted
- * value).  For LBM_FP32_SHIFTED the setter stores float(f_i - w_i rho0).
+ * lbm_set_populations / lbm_get_populations - copy the stored state f* (see
+ * above) from / to a device float64 array f[Q][N] holding f*_i (not the
+ * shifted value).  For LBM_FP32_SHIFTED the setter stores
+ * float(f*_i - w_i rho0).
  */
 int lbm_set_populations(lbm_ctx* ctx, const double* f);
 int lbm_get_populations(lbm_ctx* ctx, double* f);
 
 /*
  * lbm_step - advance n >= 0 time steps of the update rule.  Each step is one
- * kernel: gather f_i(x - e_i) (periodic, any extent), moments, 4th-order
- * equilibrium, BGK relaxation, coalesced store.  Asynchronous.
+ * kernel: gather f_i(x, t + 1) = f*_i(x - e_i, t) (periodic, any extent),
+ * moments, 4th-order equilibrium, BGK relaxation, coalesced store of
+ * f*(x, t + 1).  Asynchronous.
  */
 int lbm_step(lbm_ctx* ctx, int n);
 
@@ -205,17 +213,19 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k, size_t* bytes);
  * lbm_adjoint - gradient of a loss L(rho_n) of the density after n steps
  * with respect to the initial temperature field and omega.
  *
- * The forward map is f^0 = f^eq(rho_init, U_init, T_init), then n updates.
- * The adjoint runs backwards over the segments of a checkpointed run
- * (lbm_run_checkpointed with the same n, k, from the same initial fields):
- * per segment it recomputes the forward steps from the checkpoint while
- * storing the D+2 moments of each step, then applies the transposed step
- *   lambda^t_i(x) = (1 - omega) mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2),
- *   mu_i = lambda^{t+1}_i(x + e_i),  G_m = sum_k mu_k d f_k^eq / d m,
- * with m = (rho, rho U, sum f |e|^2) and lambda^n_i(x) = dL/drho_n(x).
- * Because the update is homogeneous of degree one in f, <lambda^t, f^t> is
- * the same constant K for every t, so
- *   dL/domega = sum_t (sum_x sum_i mu_i f_i^eq - K) / (1 - omega)
+ * The forward map is f*^0 = f^eq(rho_init, U_init, T_init), then n updates
+ * f*^{t+1} = C(S f*^t) with S the streaming and C the collision at the
+ * moments m^{t+1} of S f*^t.  The adjoint runs backwards over the segments of
+ * a checkpointed run (lbm_run_checkpointed with the same n, k, from the same
+ * initial fields): per segment it recomputes the forward steps from the
+ * checkpoint, storing the D+2 moments of each step, then applies
+ *   nu^t_i(x) = (1 - omega) mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2),
+ *   mu_i = nu^{t+1}_i(x + e_i),  G_m = sum_k mu_k d f_k^eq / d m at m^t,
+ * with m = (rho, rho U, sum f |e|^2), for t = n-1 .. 1, from
+ * nu^n_i(x) = dL/drho_n(x); dL/df*^0 is the transposed streaming of nu^1.
+ * Because the update is homogeneous of degree one in f, <dL/df*^t, f*^t> is
+ * the same constant K = sum_x dL/drho_n rho_n for every t, so
+ *   dL/domega = sum_{t=1}^{n-1} (sum_x sum_i mu_i f_i^eq(m^t) - K) / (1 - omega)
  * needs only the stored moments; it is reduced in float64.
  *
  *   ckpt, ckpt_bytes   : the checkpoints of the forward run.

@@ -534,6 +534,11 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckp
     hipError_t e = lbm::launch_fill_zero(partA, L.nA, st);
     if (e != hipSuccess) return fail_hip(ctx, e, "fill kernel");
 
+    // The kernels advance the stored (post-collision) state B as
+    // B^{t+1} = C(S B^t); the moments of S B^t are those of time t+1, and the
+    // recomputation of segment s stores them in slot j for t = t0 + j + 1.
+    // Adjoint: nu^n = dL/drho_n (broadcast over i), then for t = n-1 .. 1
+    // nu^t = C'(m^t)^T S^T nu^{t+1}, and finally dL/dB^0 = S^T nu^1.
     const int segs = (n + k - 1) / k;
     int lam = -1;   // index of the buffer holding the current adjoint state
     for (int s = segs - 1; s >= 0; --s) {
@@ -542,8 +547,6 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckp
         int fr[2], nf = 0;
         for (int b = 0; b < 3 && nf < 2; ++b)
             if (b != lam) fr[nf++] = b;
-        // recompute the segment from its checkpoint, storing the moments of
-        // every input state f^t, t = t0 .. t0 + len - 1
         e = hipMemcpyAsync(B[fr[0]], static_cast<const char*>(ckpt) + s * ck_stride, pb,
                            hipMemcpyDeviceToDevice, st);
         if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
@@ -555,19 +558,28 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckp
             std::swap(src, dst);
         }
         if (lam < 0) {
-            // last segment: B[src] holds f^n
+            // last segment: B[src] holds B^n
             lam = 3 - fr[0] - fr[1];
             e = lbm::launch_lambda_init(ctx->model, ctx->prec, ctx->kp, B[src], dL_drho_final,
                                         B[lam], partK, st);
             if (e != hipSuccess) return fail_hip(ctx, e, "adjoint initialisation kernel");
         }
-        for (int j = len - 1; j >= 0; --j) {
+        const int t_hi = std::min(t0 + len, n - 1);
+        for (int t = t_hi; t >= t0 + 1; --t) {
             const int nxt = (lam == fr[0]) ? fr[1] : fr[0];
             e = lbm::launch_adjoint_step(ctx->model, ctx->prec, ctx->kp, B[lam], B[nxt],
-                                         mom + j * L.mom_step, partA, st);
+                                         mom + (t - t0 - 1) * L.mom_step, partA, st);
             if (e != hipSuccess) return fail_hip(ctx, e, "adjoint step kernel");
             lam = nxt;
         }
+    }
+    {
+        // dL/dB^0 = S^T nu^1
+        const int nxt = (lam == 0) ? 1 : 0;
+        e = lbm::launch_adjoint_step(ctx->model, ctx->prec, ctx->kp, B[lam], B[nxt], nullptr,
+                                     nullptr, st);
+        if (e != hipSuccess) return fail_hip(ctx, e, "transposed streaming kernel");
+        lam = nxt;
     }
     if (dL_dT_init) {
         e = lbm::launch_dT_init(ctx->model, ctx->prec, ctx->kp, B[lam], rho_init, U_init, T_init,
@@ -582,7 +594,9 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckp
         e = hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return fail_hip(ctx, e, "copy of the omega gradient");
-        *dL_domega = (h[0] - static_cast<double>(n) * h[1]) / (1.0 - ctx->omega);
+        // A^t = <lambda_B^t, f^eq(m^t)> for t = 1 .. n-1; the t = n term is
+        // <lambda_B^n, f^eq(m^n)> - K = 0.
+        *dL_domega = (h[0] - static_cast<double>(n - 1) * h[1]) / (1.0 - ctx->omega);
         if (!std::isfinite(*dL_domega))
             return fail(ctx, LBM_E_NONFINITE, "omega gradient is not finite");
     }

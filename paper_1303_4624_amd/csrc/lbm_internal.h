@@ -62,6 +62,7 @@ hipError_t launch_conservation(ModelId m, Prec p, const KParams& kp, const void*
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
 hipError_t launch_lambda_init(ModelId m, Prec p, const KParams& kp, const void* fn,
                               const double* dLdrho, void* lam, double* partK, hipStream_t s);
+// mom == nullptr: transposed streaming only (no collision, partA unused).
 hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void* lam_src,
                                void* lam_dst, const void* mom, double* partA, hipStream_t s);
 hipError_t launch_dT_init(ModelId m, Prec p, const KParams& kp, const void* lam0,

@@ -488,7 +488,7 @@ __device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, do
 //   G_j   = dA/dU / rho - 2 dA/dT U / (D rho),   G_E = dA/dT / (D rho).
 // Output lambda^t_i = omc mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2).
 // partA[block] += sum over the block's cells of A = rho S0.
-template <class M, class P>
+template <class M, class P, bool COLLIDE>
 __global__ __launch_bounds__(kBlock) void k_adjoint(const typename P::S* __restrict__ lsrc,
                                                     typename P::S* __restrict__ ldst,
                                                     const typename P::S* __restrict__ mom,
@@ -502,6 +502,15 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const typename P::S* __restr
 
     S mu[Q];
     gather<M, -1>(lsrc, k, cl, mu);
+
+    if constexpr (!COLLIDE) {
+        // transposed streaming only
+        static_for<Q>([&](auto I) {
+            constexpr int i = decltype(I)::value;
+            if (cl.active) ldst[static_cast<long long>(i) * k.N + cl.c] = mu[i];
+        });
+        return;
+    }
 
     const double m0 = static_cast<double>(mom[cl.c]);
     const double ux = static_cast<double>(mom[k.N + cl.c]);
@@ -762,9 +771,16 @@ hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void*
         using M = decltype(M_);
         using P = decltype(P_);
         using S = typename P::S;
-        hipLaunchKernelGGL((k_adjoint<M, P>), dim3(static_cast<unsigned>(blocks)), dim3(kp.bx), 0,
-                           s, static_cast<const S*>(lam_src), static_cast<S*>(lam_dst),
-                           static_cast<const S*>(mom), kp, partA);
+        if (mom) {
+            hipLaunchKernelGGL((k_adjoint<M, P, true>), dim3(static_cast<unsigned>(blocks)),
+                               dim3(kp.bx), 0, s, static_cast<const S*>(lam_src),
+                               static_cast<S*>(lam_dst), static_cast<const S*>(mom), kp, partA);
+        } else {
+            hipLaunchKernelGGL((k_adjoint<M, P, false>), dim3(static_cast<unsigned>(blocks)),
+                               dim3(kp.bx), 0, s, static_cast<const S*>(lam_src),
+                               static_cast<S*>(lam_dst), static_cast<const S*>(nullptr), kp,
+                               static_cast<double*>(nullptr));
+        }
         return hipGetLastError();
     });
 }

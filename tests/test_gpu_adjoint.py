@@ -1,0 +1,154 @@
+"""The hand-written adjoint (lbm_adjoint) against the FP64 oracle's autograd
+gradient and against central finite differences of the FP64 GPU forward run.
+Bars: FP64 adjoint within 1e-9 of the oracle gradient; FP32-shifted adjoint
+within 1e-3 relative of central FD in FP64."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import new_sim
+from oracle import lbm as olbm, velocity_sets as ovs
+from synth_inputs import fd_direction, smooth_ic, target_theta
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _grad_gpu(model, extent, omega, precision, rho, U, T, n, k, target):
+    sim = new_sim(model, extent, omega, precision)
+    sim.init_fields(rho, U, T)
+    ck = sim.run_checkpointed(n, k)
+    r, _, _ = sim.moments()
+    tgt = torch.as_tensor(target, device="cuda")
+    g = 2.0 * (r - tgt)
+    L = float(((r - tgt) ** 2).sum())
+    dT, dw = sim.adjoint(n, k, ck, rho, U, T, g)
+    out = (L, dT.cpu().numpy(), dw)
+    sim.close()
+    return out
+
+
+def _loss_gpu(sim, rho, U, T, n, tgt):
+    sim.init_fields(rho, U, T)
+    sim.step(n)
+    r, _, _ = sim.moments()
+    return float(((r - tgt) ** 2).sum())
+
+
+@pytest.mark.parametrize("model,extent,n,k", [("D3Q95", (12, 8, 6), 30, 7),
+                                              ("D2Q33", (20, 12), 40, 9)])
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32s", 1e-3)])
+def test_adjoint_matches_oracle_autograd(model, extent, n, k, precision, tol):
+    _say("case", model, extent, n, k, precision)
+    v = ovs.velocity_set(model)
+    omega = 1.4
+    rho, U, th = smooth_ic(extent, seeds=(81, 82, 83, 84, 85), amp_u=0.03, amp_rho=0.02,
+                           amp_theta=0.02)
+    target = 1.0 + 0.02 * np.cos(0.7 * np.arange(np.prod(extent))).reshape(rho.shape)
+    L_o, gT_o, gw_o = olbm.loss_and_grad(v, rho, U, th * v.T0, omega, n, target)
+    gT_o = gT_o.numpy()
+    L_g, gT, gw = _grad_gpu(model, extent, omega, precision, rho, U, th * v.T0, n, k, target)
+    eT = np.max(np.abs(gT - gT_o)) / np.max(np.abs(gT_o))
+    ew = abs(gw - gw_o) / abs(gw_o)
+    _say("loss", L_g, L_o, "dT err", eT, "domega err", ew, gw, gw_o)
+    assert abs(L_g - L_o) <= (1e-12 if precision == "fp64" else 1e-5) * L_o
+    assert eT <= tol and ew <= tol
+
+
+def test_adjoint_128cube_200_steps_fp32s_vs_central_differences():
+    # Forward + adjoint in FP32-shifted storage on 128^3, 200 steps, checkpoint
+    # every 20; target from a forward run with another temperature field;
+    # directional derivatives on 8 smooth directions and omega checked by
+    # central differences of the FP64 forward run.
+    extent, n, k, omega = (128, 128, 128), 200, 20, 1.4
+    rho, U, th = smooth_ic(extent)
+    sim64 = new_sim("D3Q95", extent, omega, "fp64")
+    T0 = sim64.T0
+    T = th * T0
+    sim64.init_fields(rho, U, target_theta(extent) * T0)
+    sim64.step(n)
+    tgt, _, _ = sim64.moments()
+    tgt = tgt.clone()
+    _say("target ready")
+    L_g, gT, gw = _grad_gpu("D3Q95", extent, omega, "fp32s", rho, U, T, n, k,
+                            tgt.cpu().numpy())
+    L_c = _loss_gpu(sim64, rho, U, T, n, tgt)
+    _say("loss fp32s", L_g, "fp64", L_c)
+    worst = 0.0
+    for j in range(8):
+        d = fd_direction(extent, j) * T0
+        eps = 1e-6
+        lp = _loss_gpu(sim64, rho, U, T + eps * d, n, tgt)
+        lm = _loss_gpu(sim64, rho, U, T - eps * d, n, tgt)
+        fd = (lp - lm) / (2 * eps)
+        an = float(np.sum(gT * d))
+        err = abs(an - fd) / abs(fd)
+        worst = max(worst, err)
+        _say("direction", j, "adjoint", an, "fd", fd, "rel", err)
+    h = 1e-6
+    sim64.set_omega(omega + h)
+    lp = _loss_gpu(sim64, rho, U, T, n, tgt)
+    sim64.set_omega(omega - h)
+    lm = _loss_gpu(sim64, rho, U, T, n, tgt)
+    sim64.close()
+    fdw = (lp - lm) / (2 * h)
+    ew = abs(gw - fdw) / abs(fdw)
+    _say("omega: adjoint", gw, "fd", fdw, "rel", ew)
+    assert worst <= 1e-3 and ew <= 1e-3
+
+
+def test_fp64_adjoint_vs_central_differences_ragged_segments():
+    extent, n, k, omega = (40, 24, 16), 33, 8, 1.7
+    rho, U, th = smooth_ic(extent, seeds=(91, 92, 93, 94, 95))
+    sim = new_sim("D3Q95", extent, omega, "fp64")
+    T = th * sim.T0
+    tgt = torch.as_tensor(1.0 + 0.01 * np.sin(np.arange(np.prod(extent)) * 0.3).reshape(rho.shape),
+                          device="cuda")
+    L_g, gT, gw = _grad_gpu("D3Q95", extent, omega, "fp64", rho, U, T, n, k, tgt.cpu().numpy())
+    for j in range(3):
+        d = fd_direction(extent, j) * sim.T0
+        eps = 1e-5
+        fd = (_loss_gpu(sim, rho, U, T + eps * d, n, tgt) -
+              _loss_gpu(sim, rho, U, T - eps * d, n, tgt)) / (2 * eps)
+        an = float(np.sum(gT * d))
+        _say("direction", j, an, fd)
+        assert abs(an - fd) <= 1e-6 * abs(fd)
+    sim.set_omega(omega + 1e-5)
+    lp = _loss_gpu(sim, rho, U, T, n, tgt)
+    sim.set_omega(omega - 1e-5)
+    lm = _loss_gpu(sim, rho, U, T, n, tgt)
+    sim.close()
+    fdw = (lp - lm) / 2e-5
+    _say("omega", gw, fdw)
+    assert abs(gw - fdw) <= 1e-6 * abs(fdw)
+
+
+def test_lbmfunction_autograd_and_omega_guard():
+    from paper_1303_4624_amd import LBMFunction, _lib as L
+    extent, n, k = (16, 8, 8), 10, 4
+    rho, U, th = smooth_ic(extent, seeds=(11, 12, 13, 14, 15))
+    v = ovs.velocity_set("D3Q95")
+    target = np.full(rho.shape, 1.0)
+    _, gT_o, gw_o = olbm.loss_and_grad(v, rho, U, th * v.T0, 1.3, n, target)
+    sim = new_sim("D3Q95", extent, 1.3, "fp64")
+    T = torch.tensor(th * sim.T0, device="cuda", requires_grad=True)
+    w = torch.tensor(1.3, dtype=torch.float64, device="cuda", requires_grad=True)
+    r = LBMFunction.apply(T, w, sim, torch.tensor(rho, device="cuda"),
+                          torch.tensor(U, device="cuda"), n, k)
+    ((r - 1.0) ** 2).sum().backward()
+    assert np.max(np.abs(T.grad.cpu().numpy() - gT_o.numpy())) <= 1e-9 * np.max(np.abs(gT_o.numpy()))
+    assert abs(float(w.grad) - gw_o) <= 1e-9 * abs(gw_o)
+    # the omega gradient is divided by 1 - omega: refused at omega = 1
+    sim.set_omega(1.0)
+    sim.init_fields(rho, U, th * sim.T0)
+    ck = sim.run_checkpointed(n, k)
+    g = torch.zeros(rho.shape, dtype=torch.float64, device="cuda")
+    with pytest.raises(L.LBMError) as ex:
+        sim.adjoint(n, k, ck, rho, U, th * sim.T0, g)
+    assert ex.value.status == L.LBM_E_INVALID
+    dT, dw = sim.adjoint(n, k, ck, rho, U, th * sim.T0, g, want_omega=False)
+    assert dw is None and float(dT.abs().max()) == 0.0
+    sim.close()

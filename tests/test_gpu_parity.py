@@ -138,6 +138,22 @@ def test_populations_round_trip_and_init_matches_oracle_feq(precision):
     assert torch.equal(f, f2)
 
 
+@pytest.mark.parametrize("model,extent", [("D3Q95", (30, 7, 5)), ("D2Q33", (40, 9))])
+def test_stored_state_is_post_collision_populations(model, extent):
+    # After t steps the library stores f*(t) = (1 - omega) f(t) + omega f^eq(t),
+    # the right-hand side of the update rule (checked element by element).
+    v = ovs.velocity_set(model)
+    rho, U, th = smooth_ic(extent, seeds=(5, 6, 7, 8, 9), amp_u=0.04, amp_rho=0.03)
+    f = olbm.run(v, olbm.init_populations(v, rho, U, th * v.T0), 1.6, 9)
+    want = olbm.collide(v, f, 1.6)
+    sim = new_sim(model, extent, 1.6)
+    sim.init_fields(rho, U, th * sim.T0)
+    sim.step(9)
+    got = sim.get_populations().cpu()
+    sim.close()
+    assert torch.max(torch.abs(got - want)) <= 1e-12 * torch.max(torch.abs(want))
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32s"])
 def test_conservation_sums_match_oracle_and_are_conserved(precision):
     w = WORKLOADS["d3q95_512x4x4_riemann"]
@@ -157,7 +173,9 @@ def test_conservation_sums_match_oracle_and_are_conserved(precision):
     assert np.array_equal(c1, c1b)                 # fixed-order reduction
     drift = np.abs(c1 - c0) / scale
     _say("drift", drift)
-    assert np.all(drift <= (1e-13 if precision == "fp64" else 1e-6))
+    # FP32: per-step rounding of float32 values; on the uniform plateaus of
+    # the Riemann problem every cell rounds alike, so it adds up linearly.
+    assert np.all(drift <= (1e-13 if precision == "fp64" else 2.5e-8 * w.steps))
 
 
 def test_errors_are_reported_not_faulted():
