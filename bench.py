@@ -1,0 +1,262 @@
+"""Benchmark of the D3Q95 thermal LBM hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Headline: D3Q95 FP32-shifted, 384^3 periodic grid, omega = 1.8, seeded smooth
+random initial fields; K timed update steps (one stream-collide kernel per
+step) after W warm-up steps.  Prints ONE JSON line with MLUPS, the roofline
+of the dominant kernel (algorithmic bytes 2 Q 4 = 760 B per cell update over
+the HIP-event duration of the timed launches, against 8 TB/s HBM), the CPU
+oracle's rate on a bounded sample, and side measurements: FP64 on 256^3,
+FP32-shifted vs FP64 error after 200 steps on 256^3, and the forward +
+adjoint cost on 128^3 x 200 steps with checkpoints every 20.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "D3Q95 MLUPS & HBM GB/s vs roofline (FP32-shifted vs FP64; fwd+adjoint)"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_d3q95_fp32s_384c_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1303_4624_amd", "csrc", "lbm_kernels.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def timed_steps(sim, steps, warmup):
+    import torch
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, ev0.elapsed_time(ev1) / 1e3
+
+
+def run_headline(extent, omega, steps, warmup):
+    import torch
+    from paper_1303_4624_amd import Simulation
+    from synth_inputs import smooth_ic
+    t = time.perf_counter()
+    rho, U, th = smooth_ic(extent)
+    log(f"[bench] IC {extent} generated in {time.perf_counter() - t:.1f}s")
+    sim = Simulation("D3Q95", extent, omega, precision="fp32s", rho0=1.0)
+    sim.init_fields(rho, U, th * sim.T0)
+    del rho, U, th
+    wall, ev = timed_steps(sim, steps, warmup)
+    r, _, _ = sim.moments()
+    ok = bool(torch.isfinite(r).all())
+    cons = sim.conservation()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return wall, ev, ok, cons
+
+
+def run_fp64_and_error(extent, omega, steps_time, steps_err):
+    """FP64 throughput on `extent`, and the FP32-shifted vs FP64 GPU error
+    after `steps_err` steps from the same initial fields."""
+    import torch
+    from paper_1303_4624_amd import Simulation
+    from synth_inputs import smooth_ic
+    rho, U, th = smooth_ic(extent)
+    out = {}
+    fields = {}
+    for prec in ("fp64", "fp32s"):
+        sim = Simulation("D3Q95", extent, omega, precision=prec)
+        sim.init_fields(rho, U, th * sim.T0)
+        sim.step(steps_err)
+        fields[prec] = [x.clone() for x in sim.moments()]
+        T0 = sim.T0
+        wall, ev = timed_steps(sim, steps_time, 2)
+        out[prec] = {"mlups": sim.N * steps_time / ev / 1e6, "ms_per_step": ev / steps_time * 1e3}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    r64, u64, t64 = fields["fp64"]
+    r32, u32, t32 = fields["fp32s"]
+    err = {
+        "rho": float((r32 - r64).abs().max() / r64.abs().max()),
+        "U": float((u32 - u64).abs().max() / u64.abs().max()),
+        "T": float((t32 - t64).abs().max() / T0),
+        "steps": steps_err,
+    }
+    del fields
+    torch.cuda.empty_cache()
+    return out, err
+
+
+def run_fwd_adjoint(extent, omega, n, k):
+    """Wall time of the checkpointed forward run and of the adjoint, same stream."""
+    import torch
+    from paper_1303_4624_amd import Simulation
+    from synth_inputs import smooth_ic, target_theta
+    rho, U, th = smooth_ic(extent)
+    sim = Simulation("D3Q95", extent, omega, precision="fp32s")
+    T = th * sim.T0
+    sim.init_fields(rho, U, target_theta(extent) * sim.T0)
+    sim.step(n)
+    tgt = sim.moments()[0].clone()
+    # plain forward (no checkpoints), for reference
+    sim.init_fields(rho, U, T)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(n)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    res = {}
+    for rep in range(2):          # second repetition is the timed one
+        sim.init_fields(rho, U, T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ck = sim.run_checkpointed(n, k)
+        r = sim.moments()[0]
+        g = 2.0 * (r - tgt)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dT, dw = sim.adjoint(n, k, ck, rho, U, T, g)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = {"fwd_ms": (t1 - t0) * 1e3, "bwd_ms": (t2 - t1) * 1e3,
+               "plain_fwd_ms": t_plain * 1e3}
+        del ck, dT
+    sim.close()
+    torch.cuda.empty_cache()
+    res["ratio_total_over_fwd"] = (res["fwd_ms"] + res["bwd_ms"]) / res["fwd_ms"]
+    res["ratio_total_over_plain_fwd"] = (res["fwd_ms"] + res["bwd_ms"]) / res["plain_fwd_ms"]
+    res["grid"] = list(extent)
+    res["steps"] = n
+    res["checkpoint_every"] = k
+    return res
+
+
+def cpu_oracle_baseline(extent=(64, 64, 64), steps=20):
+    """The FP64 CPU oracle on a bounded sample of the same kind of workload."""
+    import torch
+    from oracle import lbm as olbm, velocity_sets as ovs
+    from synth_inputs import smooth_ic
+    threads = min(16, os.cpu_count() or 1)
+    torch.set_num_threads(threads)
+    v = ovs.velocity_set("D3Q95")
+    rho, U, th = smooth_ic(extent)
+    f = olbm.init_populations(v, rho, U, th * v.T0)
+    t0 = time.perf_counter()
+    f = olbm.run(v, f, 1.8, steps)
+    dt = time.perf_counter() - t0
+    cells = int(rho.size)
+    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"D3Q95 FP64 {extent[0]}x{extent[1]}x{extent[2]}, {steps} steps, "
+                      f"omega 1.8, smooth seeded IC ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--grid", type=int, default=384)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              "slab decomposition is a design, not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1303_4624_amd import _lib
+    _lib.library()            # fails loudly if the HIP library is missing
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+
+    extent = (args.grid,) * 3
+    omega = 1.8
+    Q = 95
+    log(f"[bench] headline D3Q95 fp32s {extent}, {args.steps} steps")
+    wall, ev, ok, cons = run_headline(extent, omega, args.steps, args.warmup)
+    N = args.grid ** 3
+    mlups = N * args.steps / ev / 1e6
+    per_launch_s = ev / args.steps
+    bytes_per_launch = 2 * Q * 4 * N
+    achieved = bytes_per_launch / per_launch_s / 1e9
+    traffic = measured_traffic()
+    log(f"[bench] {mlups:.1f} MLUPS, {achieved:.1f} GB/s, wall {wall:.3f}s events {ev:.3f}s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ev / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D3Q95 FP32-shifted {args.grid}^3 periodic, omega 1.8, "
+                               "seeded smooth random rho/U/T fields (wavenumbers <= 8)",
+                   "grid": list(extent), "omega": omega, "precision": "fp32s",
+                   "cell_updates_per_step": N},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic},
+        "finite": ok,
+        "mass_after": cons[0],
+    }
+    if not args.no_extras:
+        log("[bench] fp64 vs fp32s on 256^3")
+        thr, err = run_fp64_and_error((256, 256, 256), 1.5, 100, 200)
+        out["fp64_256c"] = {k: round(v, 3) for k, v in thr["fp64"].items()}
+        out["fp32s_256c"] = {k: round(v, 3) for k, v in thr["fp32s"].items()}
+        out["fp64_256c"]["roofline_frac"] = round(
+            out["fp64_256c"]["mlups"] * 1520 / 1e3 / HBM_PEAK_GBS, 4)
+        out["fp32s_vs_fp64_256c"] = err
+        log("[bench] forward + adjoint on 128^3")
+        out["fwd_adjoint_128c"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20)
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        out["cpu_baseline"] = cpu_oracle_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
