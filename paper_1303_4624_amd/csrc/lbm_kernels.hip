@@ -37,7 +37,17 @@
 namespace lbm {
 namespace {
 
-constexpr int kBlock = 256;            // threads per block of every kernel
+#ifndef LBM_STEP_MAXB
+#define LBM_STEP_MAXB 256
+#endif
+#ifndef LBM_STEP_WAVES
+#define LBM_STEP_WAVES 1
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 0
+#endif
+constexpr int kBlock = 256;            // threads per block of the cell-parallel kernels
+constexpr int kStepMaxB = LBM_STEP_MAXB;  // largest block of the row-blocked kernels
 constexpr int kW = 2 * kMaxDisp + 1;   // distinct displacement components
 
 template <class F, int... I>
@@ -216,7 +226,8 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accu
 // with omc + omega_eff = 1 exactly, so mass, momentum and energy are
 // conserved up to the rounding of each cell's own values.
 template <class M, class P, bool STORE_MOM>
-__global__ __launch_bounds__(kBlock) void k_step(const typename P::S* __restrict__ src,
+__global__ __launch_bounds__(kStepMaxB) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES)))
+void k_step(const typename P::S* __restrict__ src,
                                                  typename P::S* __restrict__ dst, KParams k,
                                                  typename P::S* __restrict__ mom) {
     using S = typename P::S;
@@ -264,7 +275,13 @@ __global__ __launch_bounds__(kBlock) void k_step(const typename P::S* __restrict
             } else {
                 out = fma(ca, h, fma(omc, v[i], ca));
             }
-            if (cl.active) dst[static_cast<long long>(i) * k.N + cl.c] = out;
+            if (cl.active) {
+#if LBM_NT_STORE
+                __builtin_nontemporal_store(out, dst + static_cast<long long>(i) * k.N + cl.c);
+#else
+                dst[static_cast<long long>(i) * k.N + cl.c] = out;
+#endif
+            }
         });
     });
 
@@ -489,7 +506,7 @@ __device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, do
 // Output lambda^t_i = omc mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2).
 // partA[block] += sum over the block's cells of A = rho S0.
 template <class M, class P, bool COLLIDE>
-__global__ __launch_bounds__(kBlock) void k_adjoint(const typename P::S* __restrict__ lsrc,
+__global__ __launch_bounds__(kStepMaxB) void k_adjoint(const typename P::S* __restrict__ lsrc,
                                                     typename P::S* __restrict__ ldst,
                                                     const typename P::S* __restrict__ mom,
                                                     KParams k, double* __restrict__ partA) {
@@ -640,9 +657,11 @@ inline unsigned cell_blocks(long long N) {
 
 }  // namespace
 
+int step_max_threads() { return kStepMaxB; }
+
 RowLaunch row_launch(int nx, long long rows, int max_threads) {
     RowLaunch r;
-    const int maxb = max_threads < kBlock ? max_threads : kBlock;
+    const int maxb = max_threads < kStepMaxB ? max_threads : kStepMaxB;
     r.chunks = (nx + maxb - 1) / maxb;
     const int per = (nx + r.chunks - 1) / r.chunks;
     r.bx = ((per + 63) / 64) * 64;

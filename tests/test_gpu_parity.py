@@ -189,3 +189,54 @@ def test_errors_are_reported_not_faulted():
         L.lbm_step(sim.ctx, 1)
     assert ex.value.status == L.LBM_E_STATE
     sim.close()
+
+
+def _patch(field, center, R):
+    """Periodic (2R+1)^D patch of a grid-shaped field (axes ..., y, x) around
+    center (x, y[, z])."""
+    out = field
+    for ax_from_end, c in enumerate(center):
+        ax = field.ndim - 1 - ax_from_end
+        n = field.shape[ax]
+        idx = np.arange(c - R, c + R + 1) % n
+        out = np.take(out, idx, axis=ax)
+    return out
+
+
+@pytest.mark.parametrize("grid,precision,tol", [(384, "fp32s", 1e-6), (256, "fp64", 1e-12)])
+def test_full_size_sampled_cells_match_oracle(grid, precision, tol):
+    # The benchmark's grid and launch configuration; a few steps; sampled
+    # cells (including ones whose stencil wraps around the periodic seams)
+    # against the oracle run on a periodic patch wide enough (radius 5n + 1)
+    # that the patch's own seam cannot reach its centre in n steps.
+    steps, omega = 3, 1.8
+    extent = (grid,) * 3
+    _say("case full size", extent, precision)
+    rho, U, th = smooth_ic(extent)
+    sim = new_sim("D3Q95", extent, omega, precision)
+    sim.init_fields(rho, U, th * sim.T0)
+    sim.step(steps)
+    r_g, u_g, t_g = sim.moments()
+    T0 = sim.T0
+    centers = [(0, 0, 0), (grid - 1, 3, grid - 2), (grid // 2, grid // 3, 7), (5, grid - 1, grid // 2),
+               (grid // 4, grid // 4, grid - 5), (grid - 3, grid // 2, 1)]
+    samples = []
+    for (x, y, z) in centers:
+        samples.append((float(r_g[z, y, x]), u_g[:, z, y, x].cpu().numpy(), float(t_g[z, y, x])))
+    sim.close()
+    del r_g, u_g, t_g
+    torch.cuda.empty_cache()
+    v = ovs.velocity_set("D3Q95")
+    R = 5 * steps + 1
+    worst = 0.0
+    for (x, y, z), (rg, ug, tg) in zip(centers, samples):
+        pr = _patch(rho, (x, y, z), R)
+        pu = np.stack([_patch(U[a], (x, y, z), R) for a in range(3)])
+        pt = _patch(th, (x, y, z), R)
+        f = olbm.run(v, olbm.init_populations(v, pr, pu, pt * v.T0), omega, steps)
+        ro, uo, to = oeq.moments(v, f)
+        ro, uo, to = float(ro[R, R, R]), uo[:, R, R, R].numpy(), float(to[R, R, R])
+        e = max(abs(rg - ro) / abs(ro), np.max(np.abs(ug - uo)) / 0.1, abs(tg - to) / T0)
+        worst = max(worst, e)
+    _say("worst sampled error", worst)
+    assert worst <= tol
