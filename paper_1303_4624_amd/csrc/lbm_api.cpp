@@ -238,6 +238,9 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
         lbm::row_launch(static_cast<int>(extent[0]), rows, lbm::step_max_threads());
     if (rl.blocks >= (1LL << 31) || rl.blocks * rl.bx >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID, "grid too large for one launch");
+    if (N * (precision == LBM_FP64 ? 8LL : 4LL) >= (1LL << 32))
+        return fail(nullptr, LBM_E_INVALID,
+                    "grid too large: one population plane must stay below 4 GiB");
     if (!omega_ok(omega)) return fail(nullptr, LBM_E_INVALID, "omega must be in [0, 2)");
     if (precision == LBM_FP32_SHIFTED && (!std::isfinite(rho0) || rho0 < 0.0))
         return fail(nullptr, LBM_E_INVALID, "rho0 must be finite and >= 0");

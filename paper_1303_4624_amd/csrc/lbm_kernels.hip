@@ -38,13 +38,25 @@ namespace lbm {
 namespace {
 
 #ifndef LBM_STEP_MAXB
-#define LBM_STEP_MAXB 256
-#endif
-#ifndef LBM_STEP_WAVES
-#define LBM_STEP_WAVES 1
+#define LBM_STEP_MAXB 512
 #endif
 #ifndef LBM_NT_STORE
-#define LBM_NT_STORE 0
+#define LBM_NT_STORE 1
+#endif
+#ifndef LBM_NT_LOAD
+#define LBM_NT_LOAD 0
+#endif
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 1
+#endif
+#ifndef LBM_ADJ_SCHED_BARRIER
+#define LBM_ADJ_SCHED_BARRIER 0
+#endif
+#ifndef LBM_ADJ_WAVES
+#define LBM_ADJ_WAVES 1
+#endif
+#ifndef LBM_F32_WAVES
+#define LBM_F32_WAVES 1
 #endif
 constexpr int kBlock = 256;            // threads per block of the cell-parallel kernels
 constexpr int kStepMaxB = LBM_STEP_MAXB;  // largest block of the row-blocked kernels
@@ -62,10 +74,14 @@ __device__ __forceinline__ void static_for(F&& f) {
 struct F64T {
     using S = double;
     static constexpr bool shifted = false;
+    static constexpr int waves = 1;
+    static constexpr int adj_waves = 1;
 };
 struct F32ST {
     using S = float;
     static constexpr bool shifted = true;
+    static constexpr int waves = LBM_F32_WAVES;
+    static constexpr int adj_waves = LBM_ADJ_WAVES;
 };
 
 // (v mod n) for v in [-kMaxDisp, n - 1 + kMaxDisp]; n is wave-uniform.
@@ -88,7 +104,16 @@ struct Cell {
 // Row-blocked mapping: block b covers threads [chunk*bx, chunk*bx + bx) of
 // grid row `row` = y + ny*z.  y and z are uniform over the block.
 __device__ __forceinline__ Cell row_cell(const KParams& k) {
+#if LBM_XCD_REMAP
+    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous range of rows so the chunks of a row share one L2.
+    const int hb = blockIdx.x;
+    const int nb = gridDim.x;
+    const int xcd = hb & 7, pos = hb >> 3, q = nb >> 3, r = nb & 7;
+    const int b = (xcd < r) ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+#else
     const int b = blockIdx.x;
+#endif
     const int chunk = b % k.chunks;
     const int row = b / k.chunks;
     Cell cl;
@@ -107,24 +132,60 @@ __device__ __forceinline__ Cell row_cell(const KParams& k) {
 template <class M, int SIGN, class S>
 __device__ __forceinline__ void gather(const S* __restrict__ src, const KParams& k, const Cell& cl,
                                        S (&v)[M::Q]) {
-    int xw[kW], yw[kW], zw[kW];
+    // Byte offsets inside one population plane fit in 32 bits (N * 8 < 2^32
+    // is checked on the host): per lane for x, wave-uniform for the y/z rows.
+    unsigned xb[kW], yb[kW], zb[kW];
     static_for<kW>([&](auto DI) {
         constexpr int d = decltype(DI)::value - kMaxDisp;
-        xw[d + kMaxDisp] = wrap_idx(cl.x - d, k.nx);
-        yw[d + kMaxDisp] = wrap_idx(cl.y - d, k.ny);
-        zw[d + kMaxDisp] = (M::D == 3) ? wrap_idx(cl.z - d, k.nz) : 0;
+        xb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.x - d, k.nx)) * sizeof(S);
+        yb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.y - d, k.ny) * k.nx) * sizeof(S);
+        zb[d + kMaxDisp] = (M::D == 3)
+            ? static_cast<unsigned>(wrap_idx(cl.z - d, k.nz)) * static_cast<unsigned>(k.nx * k.ny) *
+                  static_cast<unsigned>(sizeof(S))
+            : 0u;
     });
+    // One live 64-bit plane pointer, advanced by the plane size.
+    const char* plane = reinterpret_cast<const char*>(src);
+    const unsigned long long pbytes = static_cast<unsigned long long>(k.N) * sizeof(S);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = SIGN * M::table.e[i][0];
         constexpr int ey = SIGN * M::table.e[i][1];
         constexpr int ez = SIGN * M::table.e[i][2];
-        const long long roff =
-            (static_cast<long long>(zw[ez + kMaxDisp]) * k.ny + yw[ey + kMaxDisp]) * k.nx;
-        const S* p = src + static_cast<long long>(i) * k.N + roff;
-        v[i] = p[xw[ex + kMaxDisp]];
+        const unsigned off = zb[ez + kMaxDisp] + yb[ey + kMaxDisp] + xb[ex + kMaxDisp];
+#if LBM_NT_LOAD
+        v[i] = __builtin_nontemporal_load(reinterpret_cast<const S*>(plane + off));
+#else
+        v[i] = *reinterpret_cast<const S*>(plane + off);
+#endif
+        plane += pbytes;
     });
 }
+
+// Writes population planes in increasing order through one running 64-bit
+// plane pointer and a 32-bit byte offset of the cell inside the plane.
+// Lanes past the end of a ragged row have x clamped to 0: they compute
+// bit-identical values for cell (0, y, z) and store them there too, which
+// keeps the stores free of per-store branches.
+template <class S>
+struct PlaneWriter {
+    char* plane;
+    unsigned long long pbytes;
+    unsigned off;
+    __device__ __forceinline__ PlaneWriter(S* dst, const KParams& k, const Cell& cl)
+        : plane(reinterpret_cast<char*>(dst)),
+          pbytes(static_cast<unsigned long long>(k.N) * sizeof(S)),
+          off(static_cast<unsigned>(cl.c) * static_cast<unsigned>(sizeof(S))) {}
+    __device__ __forceinline__ void put(S val) {
+#if LBM_NT_STORE
+        __builtin_nontemporal_store(val, reinterpret_cast<S*>(plane + off));
+#else
+        *reinterpret_cast<S*>(plane + off) = val;
+#endif
+        plane += pbytes;
+    }
+};
+
 
 // Per-cell macroscopic values in float64 from the raw sums of the stored
 // values: m0 = sum v, j = sum v e, en = sum v |e|^2.
@@ -226,7 +287,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accu
 // with omc + omega_eff = 1 exactly, so mass, momentum and energy are
 // conserved up to the rounding of each cell's own values.
 template <class M, class P, bool STORE_MOM>
-__global__ __launch_bounds__(kStepMaxB) __attribute__((amdgpu_waves_per_eu(LBM_STEP_WAVES)))
+__global__ __launch_bounds__(kStepMaxB) __attribute__((amdgpu_waves_per_eu(P::waves)))
 void k_step(const typename P::S* __restrict__ src,
                                                  typename P::S* __restrict__ dst, KParams k,
                                                  typename P::S* __restrict__ mom) {
@@ -257,6 +318,7 @@ void k_step(const typename P::S* __restrict__ src,
     const double wr = k.omega_eff * mc.rho;
     const double wd = k.omega_eff * mc.dr;
     const R omc = R(k.omc);
+    PlaneWriter<S> out_w(dst, k, cl);
 
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
@@ -275,13 +337,7 @@ void k_step(const typename P::S* __restrict__ src,
             } else {
                 out = fma(ca, h, fma(omc, v[i], ca));
             }
-            if (cl.active) {
-#if LBM_NT_STORE
-                __builtin_nontemporal_store(out, dst + static_cast<long long>(i) * k.N + cl.c);
-#else
-                dst[static_cast<long long>(i) * k.N + cl.c] = out;
-#endif
-            }
+            out_w.put(out);
         });
     });
 
@@ -506,7 +562,8 @@ __device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, do
 // Output lambda^t_i = omc mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2).
 // partA[block] += sum over the block's cells of A = rho S0.
 template <class M, class P, bool COLLIDE>
-__global__ __launch_bounds__(kStepMaxB) void k_adjoint(const typename P::S* __restrict__ lsrc,
+__global__ __launch_bounds__(kStepMaxB) __attribute__((amdgpu_waves_per_eu(P::adj_waves)))
+void k_adjoint(const typename P::S* __restrict__ lsrc,
                                                     typename P::S* __restrict__ ldst,
                                                     const typename P::S* __restrict__ mom,
                                                     KParams k, double* __restrict__ partA) {
@@ -522,10 +579,8 @@ __global__ __launch_bounds__(kStepMaxB) void k_adjoint(const typename P::S* __re
 
     if constexpr (!COLLIDE) {
         // transposed streaming only
-        static_for<Q>([&](auto I) {
-            constexpr int i = decltype(I)::value;
-            if (cl.active) ldst[static_cast<long long>(i) * k.N + cl.c] = mu[i];
-        });
+        PlaneWriter<S> wt(ldst, k, cl);
+        static_for<Q>([&](auto I) { wt.put(mu[decltype(I)::value]); });
         return;
     }
 
@@ -539,7 +594,11 @@ __global__ __launch_bounds__(kStepMaxB) void k_adjoint(const typename P::S* __re
     const double u2 = usq * k.invT0;
     const R utx = R(ux * k.invT0), uty = R(uy * k.invT0), utz = R(uz * k.invT0);
 
-    R s0 = R(0), su2 = R(0), sd = R(0), ssx = R(0), ssy = R(0), ssz = R(0);
+    // Group sums in storage precision, combined with the float64 weights in
+    // float64: rounding the weights would make this the transpose of a
+    // slightly different model than the forward step and bias the omega
+    // gradient, which relies on <lambda^t, f*^t> staying constant.
+    double s0 = 0.0, su2 = 0.0, sd = 0.0, ssx = 0.0, ssy = 0.0, ssz = 0.0;
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
         const GCoef gc = group_coef(k, g, u2, d);
@@ -563,24 +622,27 @@ __global__ __launch_bounds__(kStepMaxB) void k_adjoint(const typename P::S* __re
             if constexpr (ey != 0) ty = fma(R(ey), t, ty);
             if constexpr (ez != 0) tz = fma(R(ez), t, tz);
         });
-        const R wg = R(k.W[g]);
-        s0 = fma(wg, t0, s0);
-        su2 = fma(wg, tu, su2);
-        sd = fma(wg, td, sd);
-        ssx = fma(wg, tx, ssx);
-        ssy = fma(wg, ty, ssy);
-        ssz = fma(wg, tz, ssz);
+#if LBM_ADJ_SCHED_BARRIER
+        __builtin_amdgcn_sched_barrier(0);
+#endif
+        const double wg = k.W[g];
+        s0 = fma(wg, double(t0), s0);
+        su2 = fma(wg, double(tu), su2);
+        sd = fma(wg, double(td), sd);
+        ssx = fma(wg, double(tx), ssx);
+        ssy = fma(wg, double(ty), ssy);
+        ssz = fma(wg, double(tz), ssz);
     });
 
     // chain rule in float64
     const double rT = rho * k.invT0;
-    const double aux = rT * (double(ssx) + 2.0 * ux * double(su2));
-    const double auy = rT * (double(ssy) + 2.0 * uy * double(su2));
-    const double auz = rT * (double(ssz) + 2.0 * uz * double(su2));
-    const double at = rT * double(sd);
+    const double aux = rT * (ssx + 2.0 * ux * su2);
+    const double auy = rT * (ssy + 2.0 * uy * su2);
+    const double auz = rT * (ssz + 2.0 * uz * su2);
+    const double at = rT * sd;
     const double invr = 1.0 / rho;
     const double Tm = k.T0 * (1.0 + d);
-    const double grho = double(s0) - invr * (aux * ux + auy * uy + auz * uz) +
+    const double grho = s0 - invr * (aux * ux + auy * uy + auz * uz) +
                         at * (usq - D * Tm) * invr * (1.0 / D);
     const double k2 = (2.0 / D) * at * invr;
     const double w = k.omega_eff;
@@ -590,6 +652,7 @@ __global__ __launch_bounds__(kStepMaxB) void k_adjoint(const typename P::S* __re
     const R ge = R(w * at * invr * (1.0 / D));
     const R gr = R(w * grho);
     const R omc = R(k.omc);
+    PlaneWriter<S> out_w(ldst, k, cl);
 
     static_for<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -600,10 +663,10 @@ __global__ __launch_bounds__(kStepMaxB) void k_adjoint(const typename P::S* __re
         if constexpr (ex != 0) hv = fma(R(ex), gjx, hv);
         if constexpr (ey != 0) hv = fma(R(ey), gjy, hv);
         if constexpr (ez != 0) hv = fma(R(ez), gjz, hv);
-        if (cl.active) ldst[static_cast<long long>(i) * k.N + cl.c] = fma(omc, mu[i], hv);
+        out_w.put(fma(omc, mu[i], hv));
     });
 
-    double acc[1] = {cl.active ? rho * static_cast<double>(s0) : 0.0};
+    double acc[1] = {cl.active ? rho * s0 : 0.0};
     block_sum<1>(acc, partA + blockIdx.x, true);
 }
 
