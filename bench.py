@@ -164,6 +164,28 @@ def run_fwd_adjoint(extent, omega, n, k):
     return res
 
 
+def copy_bandwidth(gib=4, reps=10):
+    """Read + write bandwidth of a plain device-to-device tensor copy (GB/s)."""
+    import torch
+    n = gib * (1 << 30) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * n * 4 / sec / 1e9
+
+
 def cpu_oracle_baseline(extent=(64, 64, 64), steps=20):
     """The FP64 CPU oracle on a bounded sample of the same kind of workload."""
     import torch
@@ -243,6 +265,9 @@ def main():
         "mass_after": cons[0],
     }
     if not args.no_extras:
+        cbw = copy_bandwidth()
+        out["roofline"]["copy_GBs"] = round(cbw, 1)
+        out["roofline"]["frac_of_copy"] = round(achieved / cbw, 4)
         log("[bench] fp64 vs fp32s on 256^3")
         thr, err = run_fp64_and_error((256, 256, 256), 1.5, 100, 200)
         out["fp64_256c"] = {k: round(v, 3) for k, v in thr["fp64"].items()}

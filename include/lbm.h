@@ -190,14 +190,18 @@ int lbm_set_omega(lbm_ctx* ctx, double omega);
 
 /*
  * lbm_checkpoint_bytes - size of the checkpoint buffer of an n-step run with
- * a checkpoint every k steps: ceil(n/k) population buffers.
+ * a checkpoint every k steps: ceil(n/k) + 1 population buffers (256-byte
+ * aligned slots) plus, for every step of the last segment, the D+2 moment
+ * planes in storage precision.
  */
 int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, size_t* bytes);
 
 /*
- * lbm_run_checkpointed - like lbm_step(n), and copies the populations at
- * t = 0, k, 2k, ... (before the step that starts each segment) into ckpt,
- * snapshot s at byte offset s * pop_bytes.  n >= 1, k >= 1.
+ * lbm_run_checkpointed - like lbm_step(n), and fills ckpt for lbm_adjoint:
+ * the stored state at t = 0, k, 2k, ... (before the step that starts each
+ * segment) in slot s = t/k, the final state in slot ceil(n/k), and the
+ * moments of each step of the last segment after the slots, so that the
+ * adjoint can start without recomputing that segment.  n >= 1, k >= 1.
  */
 int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, void* ckpt, size_t ckpt_bytes);
 
@@ -218,7 +222,8 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k, size_t* bytes);
  * moments m^{t+1} of S f*^t.  The adjoint runs backwards over the segments of
  * a checkpointed run (lbm_run_checkpointed with the same n, k, from the same
  * initial fields): per segment it recomputes the forward steps from the
- * checkpoint, storing the D+2 moments of each step, then applies
+ * checkpoint, storing the D+2 moments of each step (the last segment's were
+ * kept by the forward run), then applies
  *   nu^t_i(x) = (1 - omega) mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2),
  *   mu_i = nu^{t+1}_i(x + e_i),  G_m = sum_k mu_k d f_k^eq / d m at m^t,
  * with m = (rho, rho U, sum f |e|^2), for t = n-1 .. 1, from

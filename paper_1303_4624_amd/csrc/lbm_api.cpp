@@ -429,11 +429,35 @@ LBM_API int lbm_set_omega(lbm_ctx* ctx, double omega) {
     return LBM_OK;
 }
 
+namespace {
+
+// Checkpoint buffer of an n-step run with a snapshot every k steps:
+//   [snapshot s at t = s k, s = 0 .. segs-1][final state f*(n)]
+//   [moments of the last segment's steps, one (D+2)-plane block per step]
+// The last two parts let the adjoint start without recomputing that segment.
+struct CkLayout {
+    size_t stride, off_final, off_tail, mom_step, total;
+    int segs, len_last;
+};
+
+CkLayout ck_layout(const lbm_ctx* ctx, int n, int k) {
+    CkLayout c;
+    c.stride = round_up(pop_bytes(ctx));
+    c.segs = (n + k - 1) / k;
+    c.len_last = n - (c.segs - 1) * k;
+    c.mom_step = round_up(static_cast<size_t>(ctx->N) * (ctx->D + 2) * elem_bytes(ctx->prec));
+    c.off_final = static_cast<size_t>(c.segs) * c.stride;
+    c.off_tail = c.off_final + c.stride;
+    c.total = c.off_tail + static_cast<size_t>(c.len_last) * c.mom_step;
+    return c;
+}
+
+}  // namespace
+
 LBM_API int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, size_t* bytes) {
     if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
     if (n < 1 || k < 1 || !bytes) return fail(nullptr, LBM_E_INVALID, "need n >= 1, k >= 1");
-    const size_t segs = static_cast<size_t>((n + k - 1) / k);
-    *bytes = segs * round_up(pop_bytes(ctx));
+    *bytes = ck_layout(ctx, n, k).total;
     return LBM_OK;
 }
 
@@ -441,26 +465,31 @@ LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, void* ckpt, size_t 
     int rc;
     if ((rc = require_init(ctx)) != LBM_OK) return rc;
     if (n < 1 || k < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1");
-    size_t need = 0;
-    lbm_checkpoint_bytes(ctx, n, k, &need);
-    if (ckpt_bytes < need) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
-    if ((rc = check_dev(ctx, ckpt, need, "ckpt")) != LBM_OK) return rc;
+    const CkLayout c = ck_layout(ctx, n, k);
+    if (ckpt_bytes < c.total) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
+    if ((rc = check_dev(ctx, ckpt, c.total, "ckpt")) != LBM_OK) return rc;
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
     const size_t pb = pop_bytes(ctx);
-    const size_t stride = round_up(pb);
-    const int segs = (n + k - 1) / k;
-    for (int s = 0; s < segs; ++s) {
-        hipError_t e = hipMemcpyAsync(static_cast<char*>(ckpt) + s * stride, ctx->f[ctx->cur], pb,
-                                      hipMemcpyDeviceToDevice, ctx->stream);
-        if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
-        const int len = std::min(k, n - s * k);
-        for (int t = 0; t < len; ++t) {
-            e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
-                                 ctx->f[1 - ctx->cur], nullptr, ctx->stream);
-            if (e != hipSuccess) return fail_hip(ctx, e, "step kernel");
-            ctx->cur = 1 - ctx->cur;
-        }
+    char* ck = static_cast<char*>(ckpt);
+    // Snapshot 0 is a copy; every later snapshot is written directly by the
+    // step that ends the previous segment, and the next step reads it there.
+    hipError_t e = hipMemcpyAsync(ck, ctx->f[ctx->cur], pb, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
+    const void* src = ctx->f[ctx->cur];
+    const int t_last = (c.segs - 1) * k;   // first step of the last segment
+    for (int t = 0; t < n; ++t) {
+        const bool to_slot = ((t + 1) % k == 0) && (t + 1 < n);
+        void* dst = to_slot ? ck + ((t + 1) / k) * c.stride
+                            : (src == ctx->f[0] ? ctx->f[1] : ctx->f[0]);
+        void* mom = (t >= t_last) ? ck + c.off_tail + (t - t_last) * c.mom_step : nullptr;
+        e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, src, dst, mom, ctx->stream);
+        if (e != hipSuccess) return fail_hip(ctx, e, "step kernel");
+        src = dst;
     }
+    // the final state is in one of the context's buffers (t + 1 = n never goes to a slot)
+    ctx->cur = (src == ctx->f[0]) ? 0 : 1;
+    e = hipMemcpyAsync(ck + c.off_final, src, pb, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
     return LBM_OK;
 }
 
@@ -507,8 +536,8 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckp
     if (dL_domega && std::fabs(1.0 - ctx->omega) < 1e-3)
         return fail(ctx, LBM_E_INVALID,
                     "the omega gradient needs |1 - omega| >= 1e-3 (it is divided by 1 - omega)");
-    size_t need_ck = 0;
-    lbm_checkpoint_bytes(ctx, n, k, &need_ck);
+    const CkLayout C = ck_layout(ctx, n, k);
+    const size_t need_ck = C.total;
     if (ckpt_bytes < need_ck) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
     const AdjLayout L = adj_layout(ctx, k);
     if (ws_bytes < L.total) return fail(ctx, LBM_E_INVALID, "adjoint workspace too small");
@@ -532,8 +561,8 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckp
     double* partA = reinterpret_cast<double*>(ws + L.off_partA);
     double* partK = reinterpret_cast<double*>(ws + L.off_partK);
     double* dout = reinterpret_cast<double*>(ws + L.off_out);
-    const size_t pb = pop_bytes(ctx);
-    const size_t ck_stride = round_up(pb);
+    const size_t ck_stride = C.stride;
+    const char* ck = static_cast<const char*>(ckpt);
     hipStream_t st = ctx->stream;
     hipError_t e = lbm::launch_fill_zero(partA, L.nA, st);
     if (e != hipSuccess) return fail_hip(ctx, e, "fill kernel");
@@ -551,28 +580,33 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckp
         int fr[2], nf = 0;
         for (int b = 0; b < 3 && nf < 2; ++b)
             if (b != lam) fr[nf++] = b;
-        e = hipMemcpyAsync(B[fr[0]], static_cast<const char*>(ckpt) + s * ck_stride, pb,
-                           hipMemcpyDeviceToDevice, st);
-        if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
-        int src = fr[0], dst = fr[1];
-        for (int j = 0; j < len; ++j) {
-            e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, B[src], B[dst],
-                                 mom + j * L.mom_step, st);
-            if (e != hipSuccess) return fail_hip(ctx, e, "recompute step kernel");
-            std::swap(src, dst);
-        }
+        const char* segmom = mom;
         if (lam < 0) {
-            // last segment: B[src] holds B^n
-            lam = 3 - fr[0] - fr[1];
-            e = lbm::launch_lambda_init(ctx->model, ctx->prec, ctx->kp, B[src], dL_drho_final,
-                                        B[lam], partK, st);
+            // last segment: the forward run kept its moments and f*(n)
+            segmom = ck + C.off_tail;
+            lam = fr[0];
+            e = lbm::launch_lambda_init(ctx->model, ctx->prec, ctx->kp, ck + C.off_final,
+                                        dL_drho_final, B[lam], partK, st);
             if (e != hipSuccess) return fail_hip(ctx, e, "adjoint initialisation kernel");
+            fr[0] = 2;   // the free pair is now {1, 2}
+        } else {
+            // recompute the segment from its checkpoint (read in place),
+            // storing the moments of every step
+            const void* src = ck + s * ck_stride;
+            int dst = fr[0];
+            for (int j = 0; j < len; ++j) {
+                e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, src, B[dst],
+                                     mom + j * L.mom_step, st);
+                if (e != hipSuccess) return fail_hip(ctx, e, "recompute step kernel");
+                src = B[dst];
+                dst = (dst == fr[0]) ? fr[1] : fr[0];
+            }
         }
         const int t_hi = std::min(t0 + len, n - 1);
         for (int t = t_hi; t >= t0 + 1; --t) {
             const int nxt = (lam == fr[0]) ? fr[1] : fr[0];
             e = lbm::launch_adjoint_step(ctx->model, ctx->prec, ctx->kp, B[lam], B[nxt],
-                                         mom + (t - t0 - 1) * L.mom_step, partA, st);
+                                         segmom + (t - t0 - 1) * L.mom_step, partA, st);
             if (e != hipSuccess) return fail_hip(ctx, e, "adjoint step kernel");
             lam = nxt;
         }

@@ -603,18 +603,22 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
         constexpr int g = decltype(GI)::value;
         const GCoef gc = group_coef(k, g, u2, d);
         const GDer gd = group_der(k, g, u2, d);
-        const R a0 = R(1.0 + gc.a0), a1 = R(gc.a1), a2 = R(gc.a2), a2x2 = R(2.0 * gc.a2);
+        const R a0 = R(gc.a0), a1 = R(gc.a1), a2 = R(gc.a2), a2x2 = R(2.0 * gc.a2);
         const R b0 = R(gd.b0), c0 = R(gd.c0), c1 = R(gd.c1), c2 = R(gd.c2);
+        // sum mu P = sum mu + sum mu h with P = 1 + h: the O(1) part is summed in
+        // float64 so that the small omega signal in A is not lost to rounding.
+        double tm = 0.0;
         R t0 = R(0), tu = R(0), td = R(0), tx = R(0), ty = R(0), tz = R(0);
         static_for<M::table.gsize[g]>([&](auto JI) {
             constexpr int i = M::table.gstart[g] + decltype(JI)::value;
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const R s = edot<ex, ey, ez>(utx, uty, utz);
-            const R p = a0 + s * (a1 + s * (a2 + s * (R(1.0 / 6.0) + s * R(1.0 / 24.0))));
+            const R h = a0 + s * (a1 + s * (a2 + s * (R(1.0 / 6.0) + s * R(1.0 / 24.0))));
             const R ps = a1 + s * (a2x2 + s * (R(0.5) + s * R(1.0 / 6.0)));
             const R pu = b0 + s * (R(-0.5) - s * R(0.25));
             const R pd = c0 + s * (c1 + s * c2);
-            t0 = fma(mu[i], p, t0);
+            tm += static_cast<double>(mu[i]);
+            t0 = fma(mu[i], h, t0);
             tu = fma(mu[i], pu, tu);
             td = fma(mu[i], pd, td);
             const R t = mu[i] * ps;
@@ -626,7 +630,7 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
         __builtin_amdgcn_sched_barrier(0);
 #endif
         const double wg = k.W[g];
-        s0 = fma(wg, double(t0), s0);
+        s0 = fma(wg, tm + double(t0), s0);
         su2 = fma(wg, double(tu), su2);
         sd = fma(wg, double(td), sd);
         ssx = fma(wg, double(tx), ssx);

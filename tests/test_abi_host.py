@@ -125,9 +125,10 @@ def test_sizes_and_state_errors():
         pop, scr = L.lbm_workspace_bytes(ctx)
         assert pop == 95 * 16 * 8 * 4 * 4
         assert scr > 0 and scr % 256 == 0
-        ck = L.lbm_checkpoint_bytes(ctx, 200, 20)
-        assert ck == 10 * ((pop + 255) // 256 * 256)
-        assert L.lbm_checkpoint_bytes(ctx, 21, 20) == 2 * ((pop + 255) // 256 * 256)
+        slot = (pop + 255) // 256 * 256
+        mom = (5 * 16 * 8 * 4 * 4 + 255) // 256 * 256
+        assert L.lbm_checkpoint_bytes(ctx, 200, 20) == 11 * slot + 20 * mom
+        assert L.lbm_checkpoint_bytes(ctx, 21, 20) == 3 * slot + 1 * mom
         ws = L.lbm_adjoint_workspace_bytes(ctx, 20)
         assert ws >= 3 * pop + 20 * 5 * 16 * 8 * 4 * 4
         # unbound context: every device call is refused before touching the GPU

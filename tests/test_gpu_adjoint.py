@@ -38,7 +38,7 @@ def _loss_gpu(sim, rho, U, T, n, tgt):
     return float(((r - tgt) ** 2).sum())
 
 
-@pytest.mark.parametrize("model,extent,n,k", [("D3Q95", (12, 8, 6), 30, 7),
+@pytest.mark.parametrize("model,extent,n,k", [("D3Q95", (20, 10, 8), 10, 3),
                                               ("D2Q33", (20, 12), 40, 9)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32s", 1e-3)])
 def test_adjoint_matches_oracle_autograd(model, extent, n, k, precision, tol):
