@@ -120,8 +120,9 @@ def run_fp64_and_error(extent, omega, steps_time, steps_err):
     return out, err
 
 
-def run_fwd_adjoint(extent, omega, n, k):
-    """Wall time of the checkpointed forward run and of the adjoint, same stream."""
+def run_fwd_adjoint(extent, omega, n, k, keep=1):
+    """Wall time of the checkpointed forward run and of the adjoint, same stream.
+    `keep`: trailing segments whose step moments the forward run keeps."""
     import torch
     from paper_1303_4624_amd import Simulation
     from synth_inputs import smooth_ic, target_theta
@@ -143,12 +144,13 @@ def run_fwd_adjoint(extent, omega, n, k):
         sim.init_fields(rho, U, T)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ck = sim.run_checkpointed(n, k)
+        ck = sim.run_checkpointed(n, k, keep)
+        ck_bytes = ck.numel() * 8
         r = sim.moments()[0]
         g = 2.0 * (r - tgt)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        dT, dw = sim.adjoint(n, k, ck, rho, U, T, g)
+        dT, dw = sim.adjoint(n, k, ck, rho, U, T, g, keep=keep)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
         res = {"fwd_ms": (t1 - t0) * 1e3, "bwd_ms": (t2 - t1) * 1e3,
@@ -161,6 +163,8 @@ def run_fwd_adjoint(extent, omega, n, k):
     res["grid"] = list(extent)
     res["steps"] = n
     res["checkpoint_every"] = k
+    res["kept_segments"] = keep
+    res["checkpoint_GB"] = round(ck_bytes / 1e9, 2)
     return res
 
 
@@ -276,7 +280,9 @@ def main():
             out["fp64_256c"]["mlups"] * 1520 / 1e3 / HBM_PEAK_GBS, 4)
         out["fp32s_vs_fp64_256c"] = err
         log("[bench] forward + adjoint on 128^3")
-        out["fwd_adjoint_128c"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20)
+        out["fwd_adjoint_128c"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20, keep=1)
+        out["fwd_adjoint_128c_all_moments_kept"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20,
+                                                                   keep=10)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_oracle_baseline()

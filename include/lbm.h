@@ -190,28 +190,31 @@ int lbm_set_omega(lbm_ctx* ctx, double omega);
 
 /*
  * lbm_checkpoint_bytes - size of the checkpoint buffer of an n-step run with
- * a checkpoint every k steps: ceil(n/k) + 1 population buffers (256-byte
- * aligned slots) plus, for every step of the last segment, the D+2 moment
- * planes in storage precision.
+ * a snapshot every k steps whose last `keep` segments keep the moments of
+ * their steps: ceil(n/k) + 1 population buffers (256-byte aligned slots) plus
+ * D+2 moment planes in storage precision for each step of those segments.
+ * keep >= 1; keep >= ceil(n/k) keeps the moments of every step (the adjoint
+ * then recomputes nothing; 20 B per cell per step in LBM_FP32_SHIFTED).
  */
-int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, size_t* bytes);
+int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, int keep, size_t* bytes);
 
 /*
  * lbm_run_checkpointed - like lbm_step(n), and fills ckpt for lbm_adjoint:
  * the stored state at t = 0, k, 2k, ... (before the step that starts each
- * segment) in slot s = t/k, the final state in slot ceil(n/k), and the
- * moments of each step of the last segment after the slots, so that the
- * adjoint can start without recomputing that segment.  n >= 1, k >= 1.
+ * segment) in slot s = t/k, the final state in slot ceil(n/k), and after the
+ * slots the moments of every step of the last `keep` segments.  Snapshots
+ * after the first are written in place by the step that produces them.
+ * n >= 1, k >= 1, keep >= 1.
  */
-int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, void* ckpt, size_t ckpt_bytes);
+int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckpt, size_t ckpt_bytes);
 
 /*
  * lbm_adjoint_workspace_bytes - size of the workspace lbm_adjoint needs for
- * checkpoint interval k: three population-sized buffers (adjoint ping-pong
- * and recomputation), k steps of stored moments (D+2 values per cell per
- * step) and the float64 reduction partials.
+ * the same (n, k, keep): three population-sized buffers (adjoint ping-pong
+ * and recomputation), k steps of stored moments when some segment is
+ * recomputed, and the float64 reduction partials.
  */
-int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k, size_t* bytes);
+int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int n, int k, int keep, size_t* bytes);
 
 /*
  * lbm_adjoint - gradient of a loss L(rho_n) of the density after n steps
@@ -220,10 +223,10 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k, size_t* bytes);
  * The forward map is f*^0 = f^eq(rho_init, U_init, T_init), then n updates
  * f*^{t+1} = C(S f*^t) with S the streaming and C the collision at the
  * moments m^{t+1} of S f*^t.  The adjoint runs backwards over the segments of
- * a checkpointed run (lbm_run_checkpointed with the same n, k, from the same
- * initial fields): per segment it recomputes the forward steps from the
- * checkpoint, storing the D+2 moments of each step (the last segment's were
- * kept by the forward run), then applies
+ * a checkpointed run (lbm_run_checkpointed with the same n, k, keep, from the
+ * same initial fields): for each segment whose moments were not kept it
+ * recomputes the forward steps from the checkpoint, storing the D+2 moments
+ * of each step, then applies
  *   nu^t_i(x) = (1 - omega) mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2),
  *   mu_i = nu^{t+1}_i(x + e_i),  G_m = sum_k mu_k d f_k^eq / d m at m^t,
  * with m = (rho, rho U, sum f |e|^2), for t = n-1 .. 1, from
@@ -236,14 +239,14 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k, size_t* bytes);
  *   ckpt, ckpt_bytes   : the checkpoints of the forward run.
  *   rho_init, U_init, T_init : device float64 initial fields of that run.
  *   dL_drho_final      : device float64[N], dL/drho_n.
- *   workspace, ws_bytes: device buffer of lbm_adjoint_workspace_bytes(k).
+ *   workspace, ws_bytes: device buffer of lbm_adjoint_workspace_bytes(n, k, keep).
  *   dL_dT_init         : device float64[N] out (may be NULL).
  *   dL_domega          : host double out (may be NULL); when requested,
  *                        |1 - omega| >= 1e-3 is required (LBM_E_INVALID
  *                        otherwise) and the call synchronises the stream.
  * The context's populations are left as they were.
  */
-int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckpt_bytes,
+int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt, size_t ckpt_bytes,
                 const double* rho_init, const double* U_init, const double* T_init,
                 const double* dL_drho_final, void* workspace, size_t ws_bytes,
                 double* dL_dT_init, double* dL_domega);

@@ -64,11 +64,11 @@ _SIGS = {
     "lbm_moments": (_c.c_int, [_vp, _vp, _vp, _vp]),
     "lbm_conservation": (_c.c_int, [_vp, _pd]),
     "lbm_set_omega": (_c.c_int, [_vp, _c.c_double]),
-    "lbm_checkpoint_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _psz]),
-    "lbm_run_checkpointed": (_c.c_int, [_vp, _c.c_int, _c.c_int, _vp, _sz]),
-    "lbm_adjoint_workspace_bytes": (_c.c_int, [_vp, _c.c_int, _psz]),
-    "lbm_adjoint": (_c.c_int, [_vp, _c.c_int, _c.c_int, _vp, _sz, _vp, _vp, _vp, _vp, _vp, _sz,
-                               _vp, _pd]),
+    "lbm_checkpoint_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _psz]),
+    "lbm_run_checkpointed": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _vp, _sz]),
+    "lbm_adjoint_workspace_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _psz]),
+    "lbm_adjoint": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _vp, _sz, _vp, _vp, _vp, _vp,
+                               _vp, _sz, _vp, _pd]),
     "lbm_destroy": (_c.c_int, [_vp]),
     "lbm_status_str": (_c.c_char_p, [_c.c_int]),
     "lbm_last_error": (_c.c_char_p, [_vp]),
@@ -186,33 +186,33 @@ def lbm_set_omega(ctx, omega: float) -> None:
     _check(library().lbm_set_omega(ctx, float(omega)), "lbm_set_omega", ctx)
 
 
-def lbm_checkpoint_bytes(ctx, n: int, k: int) -> int:
+def lbm_checkpoint_bytes(ctx, n: int, k: int, keep: int = 1) -> int:
     b = _sz(0)
-    _check(library().lbm_checkpoint_bytes(ctx, int(n), int(k), ctypes.byref(b)),
+    _check(library().lbm_checkpoint_bytes(ctx, int(n), int(k), int(keep), ctypes.byref(b)),
            "lbm_checkpoint_bytes", ctx)
     return b.value
 
 
-def lbm_run_checkpointed(ctx, n: int, k: int, ckpt, ckpt_bytes: int) -> None:
-    _check(library().lbm_run_checkpointed(ctx, int(n), int(k), _addr(ckpt), int(ckpt_bytes)),
-           "lbm_run_checkpointed", ctx)
+def lbm_run_checkpointed(ctx, n: int, k: int, keep: int, ckpt, ckpt_bytes: int) -> None:
+    _check(library().lbm_run_checkpointed(ctx, int(n), int(k), int(keep), _addr(ckpt),
+                                          int(ckpt_bytes)), "lbm_run_checkpointed", ctx)
 
 
-def lbm_adjoint_workspace_bytes(ctx, k: int) -> int:
+def lbm_adjoint_workspace_bytes(ctx, n: int, k: int, keep: int = 1) -> int:
     b = _sz(0)
-    _check(library().lbm_adjoint_workspace_bytes(ctx, int(k), ctypes.byref(b)),
+    _check(library().lbm_adjoint_workspace_bytes(ctx, int(n), int(k), int(keep), ctypes.byref(b)),
            "lbm_adjoint_workspace_bytes", ctx)
     return b.value
 
 
-def lbm_adjoint(ctx, n: int, k: int, ckpt, ckpt_bytes: int, rho_init, U_init, T_init,
+def lbm_adjoint(ctx, n: int, k: int, keep: int, ckpt, ckpt_bytes: int, rho_init, U_init, T_init,
                 dL_drho_final, workspace, ws_bytes: int, dL_dT_init=None,
                 want_omega: bool = True) -> Optional[float]:
     dw = ctypes.c_double(0.0)
-    st = library().lbm_adjoint(ctx, int(n), int(k), _addr(ckpt), int(ckpt_bytes), _addr(rho_init),
-                               _addr(U_init), _addr(T_init), _addr(dL_drho_final),
-                               _addr(workspace), int(ws_bytes), _addr(dL_dT_init),
-                               ctypes.byref(dw) if want_omega else None)
+    st = library().lbm_adjoint(ctx, int(n), int(k), int(keep), _addr(ckpt), int(ckpt_bytes),
+                               _addr(rho_init), _addr(U_init), _addr(T_init),
+                               _addr(dL_drho_final), _addr(workspace), int(ws_bytes),
+                               _addr(dL_dT_init), ctypes.byref(dw) if want_omega else None)
     _check(st, "lbm_adjoint", ctx)
     return float(dw.value) if want_omega else None
 

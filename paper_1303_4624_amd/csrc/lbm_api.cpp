@@ -431,57 +431,65 @@ LBM_API int lbm_set_omega(lbm_ctx* ctx, double omega) {
 
 namespace {
 
-// Checkpoint buffer of an n-step run with a snapshot every k steps:
+// Checkpoint buffer of an n-step run with a snapshot every k steps whose
+// last `keep` segments keep their step moments:
 //   [snapshot s at t = s k, s = 0 .. segs-1][final state f*(n)]
-//   [moments of the last segment's steps, one (D+2)-plane block per step]
-// The last two parts let the adjoint start without recomputing that segment.
+//   [moments of every step t >= t_keep = (segs - keep) k, one (D+2)-plane
+//    block per step]
+// The adjoint recomputes only the segments before t_keep.
 struct CkLayout {
     size_t stride, off_final, off_tail, mom_step, total;
-    int segs, len_last;
+    int segs, keep, t_keep;
 };
 
-CkLayout ck_layout(const lbm_ctx* ctx, int n, int k) {
+CkLayout ck_layout(const lbm_ctx* ctx, int n, int k, int keep) {
     CkLayout c;
     c.stride = round_up(pop_bytes(ctx));
     c.segs = (n + k - 1) / k;
-    c.len_last = n - (c.segs - 1) * k;
+    c.keep = std::min(std::max(keep, 1), c.segs);
+    c.t_keep = (c.segs - c.keep) * k;
     c.mom_step = round_up(static_cast<size_t>(ctx->N) * (ctx->D + 2) * elem_bytes(ctx->prec));
     c.off_final = static_cast<size_t>(c.segs) * c.stride;
     c.off_tail = c.off_final + c.stride;
-    c.total = c.off_tail + static_cast<size_t>(c.len_last) * c.mom_step;
+    c.total = c.off_tail + static_cast<size_t>(n - c.t_keep) * c.mom_step;
     return c;
 }
 
 }  // namespace
 
-LBM_API int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, size_t* bytes) {
+LBM_API int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, int keep, size_t* bytes) {
     if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
-    if (n < 1 || k < 1 || !bytes) return fail(nullptr, LBM_E_INVALID, "need n >= 1, k >= 1");
-    *bytes = ck_layout(ctx, n, k).total;
+    if (n < 1 || k < 1 || keep < 1 || !bytes)
+        return fail(nullptr, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
+    *bytes = ck_layout(ctx, n, k, keep).total;
     return LBM_OK;
 }
 
-LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, void* ckpt, size_t ckpt_bytes) {
+LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckpt,
+                                 size_t ckpt_bytes) {
     int rc;
     if ((rc = require_init(ctx)) != LBM_OK) return rc;
-    if (n < 1 || k < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1");
-    const CkLayout c = ck_layout(ctx, n, k);
+    if (n < 1 || k < 1 || keep < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
+    const CkLayout c = ck_layout(ctx, n, k, keep);
     if (ckpt_bytes < c.total) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
     if ((rc = check_dev(ctx, ckpt, c.total, "ckpt")) != LBM_OK) return rc;
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
     const size_t pb = pop_bytes(ctx);
     char* ck = static_cast<char*>(ckpt);
-    // Snapshot 0 is a copy; every later snapshot is written directly by the
-    // step that ends the previous segment, and the next step reads it there.
-    hipError_t e = hipMemcpyAsync(ck, ctx->f[ctx->cur], pb, hipMemcpyDeviceToDevice, ctx->stream);
-    if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
+    // Snapshot 0 is a copy (needed only if segment 0 is recomputed); every
+    // later snapshot is written directly by the step that ends the previous
+    // segment, and the next step reads it there.
+    hipError_t e = hipSuccess;
+    if (c.t_keep > 0) {
+        e = hipMemcpyAsync(ck, ctx->f[ctx->cur], pb, hipMemcpyDeviceToDevice, ctx->stream);
+        if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
+    }
     const void* src = ctx->f[ctx->cur];
-    const int t_last = (c.segs - 1) * k;   // first step of the last segment
     for (int t = 0; t < n; ++t) {
         const bool to_slot = ((t + 1) % k == 0) && (t + 1 < n);
         void* dst = to_slot ? ck + ((t + 1) / k) * c.stride
                             : (src == ctx->f[0] ? ctx->f[1] : ctx->f[0]);
-        void* mom = (t >= t_last) ? ck + c.off_tail + (t - t_last) * c.mom_step : nullptr;
+        void* mom = (t >= c.t_keep) ? ck + c.off_tail + (t - c.t_keep) * c.mom_step : nullptr;
         e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, src, dst, mom, ctx->stream);
         if (e != hipSuccess) return fail_hip(ctx, e, "step kernel");
         src = dst;
@@ -502,14 +510,14 @@ struct AdjLayout {
     long long nA, nK;
 };
 
-AdjLayout adj_layout(const lbm_ctx* ctx, int k) {
+AdjLayout adj_layout(const lbm_ctx* ctx, int k, bool recompute) {
     AdjLayout L;
     L.pop = round_up(pop_bytes(ctx));
     L.mom_step = round_up(static_cast<size_t>(ctx->N) * (ctx->D + 2) * elem_bytes(ctx->prec));
     L.off_mom = 3 * L.pop;
     L.nA = lbm::step_blocks(ctx->model, ctx->prec, ctx->kp);
     L.nK = (ctx->N + 255) / 256;
-    L.off_partA = L.off_mom + static_cast<size_t>(k) * L.mom_step;
+    L.off_partA = L.off_mom + (recompute ? static_cast<size_t>(k) * L.mom_step : 0);
     L.off_partK = L.off_partA + round_up(static_cast<size_t>(L.nA) * 8);
     L.off_out = L.off_partK + round_up(static_cast<size_t>(L.nK) * 8);
     L.total = L.off_out + round_up(2 * 8);
@@ -518,28 +526,32 @@ AdjLayout adj_layout(const lbm_ctx* ctx, int k) {
 
 }  // namespace
 
-LBM_API int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int k, size_t* bytes) {
+LBM_API int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int n, int k, int keep,
+                                        size_t* bytes) {
     if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
-    if (k < 1 || !bytes) return fail(nullptr, LBM_E_INVALID, "need k >= 1");
-    *bytes = adj_layout(ctx, k).total;
+    if (n < 1 || k < 1 || keep < 1 || !bytes)
+        return fail(nullptr, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
+    *bytes = adj_layout(ctx, k, ck_layout(ctx, n, k, keep).t_keep > 0).total;
     return LBM_OK;
 }
 
-LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckpt_bytes,
+LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
+                        size_t ckpt_bytes,
                         const double* rho_init, const double* U_init, const double* T_init,
                         const double* dL_drho_final, void* workspace, size_t ws_bytes,
                         double* dL_dT_init, double* dL_domega) {
     int rc;
     if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
     if (!ctx->bound) return fail(ctx, LBM_E_STATE, "no buffers bound (call lbm_bind)");
-    if (n < 1 || k < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1");
+    if (n < 1 || k < 1 || keep < 1)
+        return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
     if (dL_domega && std::fabs(1.0 - ctx->omega) < 1e-3)
         return fail(ctx, LBM_E_INVALID,
                     "the omega gradient needs |1 - omega| >= 1e-3 (it is divided by 1 - omega)");
-    const CkLayout C = ck_layout(ctx, n, k);
+    const CkLayout C = ck_layout(ctx, n, k, keep);
     const size_t need_ck = C.total;
     if (ckpt_bytes < need_ck) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
-    const AdjLayout L = adj_layout(ctx, k);
+    const AdjLayout L = adj_layout(ctx, k, C.t_keep > 0);
     if (ws_bytes < L.total) return fail(ctx, LBM_E_INVALID, "adjoint workspace too small");
     const size_t nb = static_cast<size_t>(ctx->N) * 8;
     if ((rc = check_dev(ctx, ckpt, need_ck, "ckpt")) != LBM_OK) return rc;
@@ -582,13 +594,16 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, const void* ckpt, size_t ckp
             if (b != lam) fr[nf++] = b;
         const char* segmom = mom;
         if (lam < 0) {
-            // last segment: the forward run kept its moments and f*(n)
-            segmom = ck + C.off_tail;
+            // start from f*(n), kept by the forward run
             lam = fr[0];
             e = lbm::launch_lambda_init(ctx->model, ctx->prec, ctx->kp, ck + C.off_final,
                                         dL_drho_final, B[lam], partK, st);
             if (e != hipSuccess) return fail_hip(ctx, e, "adjoint initialisation kernel");
             fr[0] = 2;   // the free pair is now {1, 2}
+        }
+        if (t0 >= C.t_keep) {
+            // the forward run kept this segment's moments
+            segmom = ck + C.off_tail + static_cast<size_t>(t0 - C.t_keep) * C.mom_step;
         } else {
             // recompute the segment from its checkpoint (read in place),
             // storing the moments of every step

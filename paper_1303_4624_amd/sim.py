@@ -106,24 +106,26 @@ class Simulation:
         L.lbm_set_omega(self.ctx, omega)
         self.omega = float(omega)
 
-    def run_checkpointed(self, n: int, k: int) -> torch.Tensor:
-        nb = L.lbm_checkpoint_bytes(self.ctx, n, k)
+    def run_checkpointed(self, n: int, k: int, keep: int = 1) -> torch.Tensor:
+        """n steps with a snapshot every k steps; the last `keep` segments also
+        keep their step moments (keep >= ceil(n/k): no recomputation later)."""
+        nb = L.lbm_checkpoint_bytes(self.ctx, n, k, keep)
         ck = _dev_bytes(nb, self.device)
-        L.lbm_run_checkpointed(self.ctx, n, k, ck, nb)
+        L.lbm_run_checkpointed(self.ctx, n, k, keep, ck, nb)
         return ck
 
     def adjoint(self, n: int, k: int, ckpt: torch.Tensor, rho_init, U_init, T_init,
                 dL_drho_final, want_T: bool = True, want_omega: bool = True,
-                workspace: Optional[torch.Tensor] = None):
+                workspace: Optional[torch.Tensor] = None, keep: int = 1):
         """(dL/dT_init as a grid-shaped tensor or None, dL/domega or None)."""
-        wsb = L.lbm_adjoint_workspace_bytes(self.ctx, k)
+        wsb = L.lbm_adjoint_workspace_bytes(self.ctx, n, k, keep)
         if workspace is None or workspace.numel() * 8 < wsb:
             workspace = _dev_bytes(wsb, self.device)
         r, u, t = self._field(rho_init), self._field(U_init, self.D), self._field(T_init)
         g = self._field(dL_drho_final)
         dT = torch.empty(self.grid_shape, dtype=torch.float64, device=self.device) if want_T else None
-        dw = L.lbm_adjoint(self.ctx, n, k, ckpt, ckpt.numel() * 8, r, u, t, g, workspace, wsb,
-                           dT, want_omega)
+        dw = L.lbm_adjoint(self.ctx, n, k, keep, ckpt, ckpt.numel() * 8, r, u, t, g, workspace,
+                           wsb, dT, want_omega)
         self._keep = (r, u, t, g, workspace)
         return dT, dw
 

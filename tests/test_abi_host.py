@@ -128,9 +128,13 @@ def test_sizes_and_state_errors():
         slot = (pop + 255) // 256 * 256
         mom = (5 * 16 * 8 * 4 * 4 + 255) // 256 * 256
         assert L.lbm_checkpoint_bytes(ctx, 200, 20) == 11 * slot + 20 * mom
+        assert L.lbm_checkpoint_bytes(ctx, 200, 20, 3) == 11 * slot + 60 * mom
+        assert L.lbm_checkpoint_bytes(ctx, 200, 20, 99) == 11 * slot + 200 * mom
         assert L.lbm_checkpoint_bytes(ctx, 21, 20) == 3 * slot + 1 * mom
-        ws = L.lbm_adjoint_workspace_bytes(ctx, 20)
-        assert ws >= 3 * pop + 20 * 5 * 16 * 8 * 4 * 4
+        ws = L.lbm_adjoint_workspace_bytes(ctx, 200, 20, 1)
+        assert ws >= 3 * pop + 20 * mom
+        # every segment's moments kept: no recomputation, no moment workspace
+        assert L.lbm_adjoint_workspace_bytes(ctx, 200, 20, 10) < 3 * slot + mom
         # unbound context: every device call is refused before touching the GPU
         for fn, args in [(L.lbm_step, (1,)), (L.lbm_moments, (None, None, None)),
                          (L.lbm_get_populations, (0,)), (L.lbm_init_fields, (0, 0, 0))]:
@@ -143,6 +147,9 @@ def test_sizes_and_state_errors():
         L.lbm_set_omega(ctx, 1.7)
         with pytest.raises(L.LBMError) as ex:
             L.lbm_checkpoint_bytes(ctx, 0, 20)
+        assert ex.value.status == L.LBM_E_INVALID
+        with pytest.raises(L.LBMError) as ex:
+            L.lbm_checkpoint_bytes(ctx, 10, 2, 0)
         assert ex.value.status == L.LBM_E_INVALID
     finally:
         L.lbm_destroy(ctx)

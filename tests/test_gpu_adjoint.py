@@ -17,15 +17,15 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def _grad_gpu(model, extent, omega, precision, rho, U, T, n, k, target):
+def _grad_gpu(model, extent, omega, precision, rho, U, T, n, k, target, keep=1):
     sim = new_sim(model, extent, omega, precision)
     sim.init_fields(rho, U, T)
-    ck = sim.run_checkpointed(n, k)
+    ck = sim.run_checkpointed(n, k, keep)
     r, _, _ = sim.moments()
     tgt = torch.as_tensor(target, device="cuda")
     g = 2.0 * (r - tgt)
     L = float(((r - tgt) ** 2).sum())
-    dT, dw = sim.adjoint(n, k, ck, rho, U, T, g)
+    dT, dw = sim.adjoint(n, k, ck, rho, U, T, g, keep=keep)
     out = (L, dT.cpu().numpy(), dw)
     sim.close()
     return out
@@ -63,6 +63,21 @@ def test_adjoint_matches_oracle_autograd(model, extent, n, k, precision, tol):
     _say("loss", L_g, L_o, "dT err", eT, "domega err", ew, gw, gw_o)
     assert abs(L_g - L_o) <= (1e-12 if precision == "fp64" else 1e-5) * L_o
     assert eT <= tol and ew <= tol
+
+
+@pytest.mark.parametrize("keep", [2, 99])
+def test_kept_moments_give_the_same_gradient(keep):
+    # Keeping the step moments of more segments only removes recomputation;
+    # the kernels and their inputs are the same, so the result is bitwise equal.
+    extent, n, k, omega = (24, 10, 8), 17, 5, 1.3
+    rho, U, th = smooth_ic(extent, seeds=(31, 32, 33, 34, 35))
+    sim = new_sim("D3Q95", extent, omega, "fp32s")
+    T = th * sim.T0
+    sim.close()
+    tgt = 1.0 + 0.01 * smooth_noise(extent, 36)
+    a = _grad_gpu("D3Q95", extent, omega, "fp32s", rho, U, T, n, k, tgt, keep=1)
+    b = _grad_gpu("D3Q95", extent, omega, "fp32s", rho, U, T, n, k, tgt, keep=keep)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1]) and a[2] == b[2]
 
 
 def test_adjoint_128cube_200_steps_fp32s_vs_central_differences():
@@ -144,7 +159,7 @@ def test_lbmfunction_autograd_and_omega_guard():
     T = torch.tensor(th * sim.T0, device="cuda", requires_grad=True)
     w = torch.tensor(1.3, dtype=torch.float64, device="cuda", requires_grad=True)
     r = LBMFunction.apply(T, w, sim, torch.tensor(rho, device="cuda"),
-                          torch.tensor(U, device="cuda"), n, k)
+                          torch.tensor(U, device="cuda"), n, k, 1)
     ((r - 1.0) ** 2).sum().backward()
     assert np.max(np.abs(T.grad.cpu().numpy() - gT_o.numpy())) <= 1e-9 * np.max(np.abs(gT_o.numpy()))
     assert abs(float(w.grad) - gw_o) <= 1e-9 * abs(gw_o)
