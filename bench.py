@@ -218,6 +218,8 @@ def main():
     ap.add_argument("--grid", type=int, default=384)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 2 GiB device copy first (reference dispatch for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -232,6 +234,16 @@ def main():
         sys.exit(2)
     torch.cuda.set_device(0)
 
+    if args.copy_calibration:
+        n = (1 << 31) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        torch.cuda.empty_cache()
+        log("[bench] calibration copy of 2 GiB done")
     extent = (args.grid,) * 3
     omega = 1.8
     Q = 95
