@@ -64,8 +64,11 @@ int fail_hip(lbm_ctx* ctx, hipError_t e, const char* what) {
 
 size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
+// Elements between two population planes of the stored state.
+long long plane_stride(const lbm_ctx* ctx) { return ctx->N + lbm::kPlanePad; }
+
 size_t pop_bytes(const lbm_ctx* ctx) {
-    return static_cast<size_t>(ctx->N) * ctx->Q * elem_bytes(ctx->prec);
+    return static_cast<size_t>(plane_stride(ctx)) * ctx->Q * elem_bytes(ctx->prec);
 }
 
 size_t scratch_bytes(const lbm_ctx* ctx) {
@@ -113,6 +116,7 @@ void fill_kparams(lbm_ctx* ctx) {
     k.ny = static_cast<int>(ctx->extent[1]);
     k.nz = ctx->D == 3 ? static_cast<int>(ctx->extent[2]) : 1;
     k.N = ctx->N;
+    k.P = plane_stride(ctx);
     const long long rows = static_cast<long long>(k.ny) * k.nz;
     const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads());
     k.chunks = rl.chunks;
@@ -238,7 +242,7 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
         lbm::row_launch(static_cast<int>(extent[0]), rows, lbm::step_max_threads());
     if (rl.blocks >= (1LL << 31) || rl.blocks * rl.bx >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID, "grid too large for one launch");
-    if (N * (precision == LBM_FP64 ? 8LL : 4LL) >= (1LL << 32))
+    if ((N + lbm::kPlanePad) * (precision == LBM_FP64 ? 8LL : 4LL) >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID,
                     "grid too large: one population plane must stay below 4 GiB");
     if (!omega_ok(omega)) return fail(nullptr, LBM_E_INVALID, "omega must be in [0, 2)");

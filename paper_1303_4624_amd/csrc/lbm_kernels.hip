@@ -146,7 +146,7 @@ __device__ __forceinline__ void gather(const S* __restrict__ src, const KParams&
     });
     // One live 64-bit plane pointer, advanced by the plane size.
     const char* plane = reinterpret_cast<const char*>(src);
-    const unsigned long long pbytes = static_cast<unsigned long long>(k.N) * sizeof(S);
+    const unsigned long long pbytes = static_cast<unsigned long long>(k.P) * sizeof(S);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = SIGN * M::table.e[i][0];
@@ -174,7 +174,7 @@ struct PlaneWriter {
     unsigned off;
     __device__ __forceinline__ PlaneWriter(S* dst, const KParams& k, const Cell& cl)
         : plane(reinterpret_cast<char*>(dst)),
-          pbytes(static_cast<unsigned long long>(k.N) * sizeof(S)),
+          pbytes(static_cast<unsigned long long>(k.P) * sizeof(S)),
           off(static_cast<unsigned>(cl.c) * static_cast<unsigned>(sizeof(S))) {}
     __device__ __forceinline__ void put(S val) {
 #if LBM_NT_STORE
@@ -377,10 +377,10 @@ __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ rho,
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double h = horner_h(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
             if constexpr (P::shifted) {
-                f[static_cast<long long>(i) * k.N + c] =
+                f[static_cast<long long>(i) * k.P + c] =
                     static_cast<float>(w * (r - k.rho0) + w * r * h);
             } else {
-                f[static_cast<long long>(i) * k.N + c] = w * r * (1.0 + h);
+                f[static_cast<long long>(i) * k.P + c] = w * r * (1.0 + h);
             }
         });
     });
@@ -397,9 +397,9 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(const double* __restrict__ f
         constexpr int g = M::table.group[i];
         const double val = fin[static_cast<long long>(i) * k.N + c];
         if constexpr (P::shifted)
-            f[static_cast<long long>(i) * k.N + c] = static_cast<float>(val - k.W[g] * k.rho0);
+            f[static_cast<long long>(i) * k.P + c] = static_cast<float>(val - k.W[g] * k.rho0);
         else
-            f[static_cast<long long>(i) * k.N + c] = val;
+            f[static_cast<long long>(i) * k.P + c] = val;
     });
 }
 
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(const typename P::S* __restr
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int g = M::table.group[i];
-        const double val = static_cast<double>(f[static_cast<long long>(i) * k.N + c]);
+        const double val = static_cast<double>(f[static_cast<long long>(i) * k.P + c]);
         fout[static_cast<long long>(i) * k.N + c] = P::shifted ? val + k.W[g] * k.rho0 : val;
     });
 }
@@ -427,7 +427,7 @@ __device__ __forceinline__ void cell_sums(const S* __restrict__ f, const KParams
         constexpr int i = decltype(I)::value;
         constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
         constexpr int ee = M::table.e2[M::table.group[i]];
-        const double val = static_cast<double>(f[static_cast<long long>(i) * k.N + c]);
+        const double val = static_cast<double>(f[static_cast<long long>(i) * k.P + c]);
         m0 += val;
         if constexpr (ex != 0) j[0] += double(ex) * val;
         if constexpr (ey != 0) j[1] += double(ey) * val;
@@ -525,8 +525,8 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
         double m0 = 0.0;
         static_for<M::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            m0 += static_cast<double>(fn[static_cast<long long>(i) * k.N + c]);
-            lam[static_cast<long long>(i) * k.N + c] = static_cast<S>(g);
+            m0 += static_cast<double>(fn[static_cast<long long>(i) * k.P + c]);
+            lam[static_cast<long long>(i) * k.P + c] = static_cast<S>(g);
         });
         const double r = P::shifted ? k.rho0 + m0 : m0;
         acc[0] = g * r;
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double s = edot<ex, ey, ez>(utx, uty, utz);
             const double pd = gd.c0 + s * (gd.c1 + s * gd.c2);
-            tg += static_cast<double>(lam[static_cast<long long>(i) * k.N + c]) * pd;
+            tg += static_cast<double>(lam[static_cast<long long>(i) * k.P + c]) * pd;
         });
         sd += k.W[g] * tg;
     });
