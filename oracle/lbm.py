@@ -11,6 +11,14 @@ extent are handled).  This is the same map as gathering from x - e_i.
 
 Initial state: f = f^eq(rho, U, T) of the given fields, which is how the
 paper's shock-tube experiment states its homogeneous initial conditions.
+
+End conditions of the shock tube (results section): the two end planes
+normal to the tube axis (the slowest grid axis) carry the fixed states C_L
+and C_R while the side directions stay periodic.  Read here as reservoirs:
+after every update the populations of the first n_lo and the last n_hi
+planes are replaced by f^eq of the fixed state.  Since a node gathers from
+up to max|e_z| planes away, holding that many planes at each end keeps the
+periodic seam closed.
 """
 from __future__ import annotations
 
@@ -52,13 +60,37 @@ def stream(vs: VelocitySet, post: torch.Tensor) -> torch.Tensor:
     return torch.stack(outs)
 
 
-def step(vs: VelocitySet, f: torch.Tensor, omega) -> torch.Tensor:
-    return stream(vs, collide(vs, f, omega))
+def hold_planes(vs: VelocitySet, f: torch.Tensor, n_lo: int, n_hi: int,
+                state_lo=None, state_hi=None) -> torch.Tensor:
+    """f with planes [0, n_lo) and [L - n_hi, L) of the slowest grid axis set
+    to f^eq(state); a state is (rho, U_x, U_y[, U_z], T)."""
+    D = vs.D
+    f = f.clone()
+    L = f.shape[1]
+    plane = f.shape[2:]
+    for lo, hi, st in ((0, n_lo, state_lo), (L - n_hi, L, state_hi)):
+        if hi <= lo:
+            continue
+        st = [float(x) for x in st]
+        rho = torch.full(plane, st[0], dtype=torch.float64)
+        U = torch.stack([torch.full(plane, st[1 + a], dtype=torch.float64) for a in range(D)])
+        T = torch.full(plane, st[D + 1], dtype=torch.float64)
+        f[:, lo:hi] = feq(vs, rho, U, T).unsqueeze(1)
+    return f
 
 
-def run(vs: VelocitySet, f: torch.Tensor, omega, n: int) -> torch.Tensor:
+def step(vs: VelocitySet, f: torch.Tensor, omega, hold=None) -> torch.Tensor:
+    """One update; ``hold`` = (n_lo, n_hi, state_lo, state_hi) applies the
+    fixed end planes afterwards."""
+    f = stream(vs, collide(vs, f, omega))
+    if hold is not None:
+        f = hold_planes(vs, f, *hold)
+    return f
+
+
+def run(vs: VelocitySet, f: torch.Tensor, omega, n: int, hold=None) -> torch.Tensor:
     for _ in range(n):
-        f = step(vs, f, omega)
+        f = step(vs, f, omega, hold)
     return f
 
 

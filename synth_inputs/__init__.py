@@ -31,6 +31,8 @@ __all__ = [
     "smooth_ic",
     "riemann_ic",
     "double_riemann_ic",
+    "tube_ic",
+    "tube_states",
     "workload_ic",
     "fd_direction",
     "target_theta",
@@ -71,6 +73,15 @@ WORKLOADS: Dict[str, Workload] = {
         # Throughput / roofline run.
         Workload("d3q95_384c_smooth", "D3Q95", (384, 384, 384), 1.8, 500,
                  "smooth", ("fp32s",)),
+        # The shock tube of the results section: 11 x 11 x 800 nodes, the left
+        # half (z < 400) at rho = p = 4, the right half at rho = p = 1, theta = 1
+        # and at rest in both; the end planes held at those states
+        # (extra["hold"] planes at each end), sides periodic, omega = 1.5.
+        Workload("d3q95_11x11x800_tube", "D3Q95", (11, 11, 800), 1.5, 120,
+                 "tube", ("fp64", "fp32s"), extra={"hold": 5}),
+        # The same tube for the 2D model along y.
+        Workload("d2q33_11x800_tube", "D2Q33", (11, 800), 1.5, 120,
+                 "tube", ("fp64", "fp32s"), extra={"hold": 4}),
         # Forward + adjoint with checkpoints every 20 steps.
         Workload("d3q95_128c_adjoint", "D3Q95", (128, 128, 128), 1.4, 200,
                  "smooth", ("fp32s",), checkpoint_every=20),
@@ -146,6 +157,22 @@ def riemann_ic(extent, x_split, left, right):
     return rho, U, theta
 
 
+def tube_ic(extent, split, left, right):
+    """Two homogeneous states at rest split along the slowest axis (z in 3D,
+    y in 2D): index < split gets ``left``, else ``right``; (rho, theta) pairs."""
+    shape = grid_shape(extent)
+    z = np.broadcast_to(np.arange(extent[-1]).reshape((-1,) + (1,) * (len(extent) - 1)), shape)
+    rho = np.where(z < split, left[0], right[0]).astype(np.float64)
+    theta = np.where(z < split, left[1], right[1]).astype(np.float64)
+    U = np.zeros((len(extent),) + rho.shape)
+    return rho, U, theta
+
+
+def tube_states(w: Workload):
+    """(left, right) (rho, theta) pairs of a tube workload."""
+    return (4.0, 1.0), (1.0, 1.0)
+
+
 def double_riemann_ic(extent, x_lo, x_hi, outer, inner):
     """``inner`` state for x_lo <= x < x_hi, ``outer`` elsewhere; U = 0."""
     x = _x_index(extent)
@@ -170,6 +197,9 @@ def workload_ic(w: Workload, extent=None):
         return riemann_ic(ext, ext[0] // 2, (1.0, 1.0), (0.5, 0.8))
     if w.ic == "smooth":
         return smooth_ic(ext)
+    if w.ic == "tube":
+        lo, hi = tube_states(w)
+        return tube_ic(ext, ext[-1] // 2, lo, hi)
     raise ValueError(w.ic)
 
 

@@ -153,3 +153,29 @@ def test_sizes_and_state_errors():
         assert ex.value.status == L.LBM_E_INVALID
     finally:
         L.lbm_destroy(ctx)
+
+
+@pytest.mark.parametrize("name", list(MODELS))
+def test_fixed_planes_validation(name):
+    D, _ = MODELS[name]
+    kw = _args(name, extent=[6] * (D - 1) + [20])
+    ctx = L.lbm_create(**kw)
+    good = [1.0] + [0.0] * D + [1.0]
+    try:
+        L.lbm_set_fixed_planes(ctx, 5, 5, good, good)
+        L.lbm_set_fixed_planes(ctx, 20, 0, good, None)
+        L.lbm_set_fixed_planes(ctx, 0, 0, None, None)
+        cases = [
+            ((-1, 0, good, good), L.LBM_E_INVALID),
+            ((11, 10, good, good), L.LBM_E_INVALID),          # more planes than the axis has
+            ((1, 1, good, None), L.LBM_E_INVALID),
+            ((1, 1, [0.0] + good[1:], good), L.LBM_E_INVALID),   # rho <= 0
+            ((1, 1, good, good[:-1] + [-2.0]), L.LBM_E_INVALID),  # T <= 0
+            ((1, 1, good[:1] + [float("nan")] + good[2:], good), L.LBM_E_NONFINITE),
+        ]
+        for args, want in cases:
+            with pytest.raises(L.LBMError) as ex:
+                L.lbm_set_fixed_planes(ctx, *args)
+            assert ex.value.status == want, args
+    finally:
+        L.lbm_destroy(ctx)

@@ -203,39 +203,58 @@ def _patch(field, center, R):
     return out
 
 
-@pytest.mark.parametrize("grid,precision,tol", [(384, "fp32s", 1e-6), (256, "fp64", 1e-12)])
-def test_full_size_sampled_cells_match_oracle(grid, precision, tol):
-    # The benchmark's grid and launch configuration; a few steps; sampled
+def _centers(extent):
+    """Sample cells: corners (stencils wrapping two seams), edges, interior."""
+    if len(extent) == 3:
+        g = extent[0]
+        return [(0, 0, 0), (g - 1, 3, g - 2), (g // 2, g // 3, 7), (5, g - 1, g // 2),
+                (g // 4, g // 4, g - 5), (g - 3, g // 2, 1)]
+    nx, ny = extent
+    return [(0, 0), (nx - 1, ny - 2), (nx // 2, 3), (2, ny // 3), (nx // 3, ny - 1),
+            (nx - 4, ny // 2)]
+
+
+@pytest.mark.parametrize("model,extent,precision,tol", [
+    ("D3Q95", (384,) * 3, "fp32s", 1e-6),
+    ("D3Q95", (256,) * 3, "fp64", 1e-12),
+    ("D2Q33", (8192,) * 2, "fp32s", 1e-6),
+    ("D2Q33", (8192,) * 2, "fp64", 1e-12),
+])
+def test_full_size_sampled_cells_match_oracle(model, extent, precision, tol):
+    # The benchmark's grids and launch configuration; a few steps; sampled
     # cells (including ones whose stencil wraps around the periodic seams)
-    # against the oracle run on a periodic patch wide enough (radius 5n + 1)
-    # that the patch's own seam cannot reach its centre in n steps.
+    # against the oracle run on a periodic patch wide enough (radius m n + 1,
+    # m the largest displacement component) that the patch's own seam cannot
+    # reach its centre in n steps.
     steps, omega = 3, 1.8
-    extent = (grid,) * 3
-    _say("case full size", extent, precision)
+    D = len(extent)
+    _say("case full size", model, extent, precision)
     rho, U, th = smooth_ic(extent)
-    sim = new_sim("D3Q95", extent, omega, precision)
+    sim = new_sim(model, extent, omega, precision)
     sim.init_fields(rho, U, th * sim.T0)
     sim.step(steps)
     r_g, u_g, t_g = sim.moments()
     T0 = sim.T0
-    centers = [(0, 0, 0), (grid - 1, 3, grid - 2), (grid // 2, grid // 3, 7), (5, grid - 1, grid // 2),
-               (grid // 4, grid // 4, grid - 5), (grid - 3, grid // 2, 1)]
+    centers = _centers(extent)
     samples = []
-    for (x, y, z) in centers:
-        samples.append((float(r_g[z, y, x]), u_g[:, z, y, x].cpu().numpy(), float(t_g[z, y, x])))
+    for c in centers:
+        idx = tuple(reversed(c))
+        samples.append((float(r_g[idx]), u_g[(slice(None),) + idx].cpu().numpy(),
+                        float(t_g[idx])))
     sim.close()
     del r_g, u_g, t_g
     torch.cuda.empty_cache()
-    v = ovs.velocity_set("D3Q95")
-    R = 5 * steps + 1
+    v = ovs.velocity_set(model)
+    R = int(np.abs(v.e).max()) * steps + 1
+    mid = (R,) * D
     worst = 0.0
-    for (x, y, z), (rg, ug, tg) in zip(centers, samples):
-        pr = _patch(rho, (x, y, z), R)
-        pu = np.stack([_patch(U[a], (x, y, z), R) for a in range(3)])
-        pt = _patch(th, (x, y, z), R)
+    for c, (rg, ug, tg) in zip(centers, samples):
+        pr = _patch(rho, c, R)
+        pu = np.stack([_patch(U[a], c, R) for a in range(D)])
+        pt = _patch(th, c, R)
         f = olbm.run(v, olbm.init_populations(v, pr, pu, pt * v.T0), omega, steps)
         ro, uo, to = oeq.moments(v, f)
-        ro, uo, to = float(ro[R, R, R]), uo[:, R, R, R].numpy(), float(to[R, R, R])
+        ro, uo, to = float(ro[mid]), uo[(slice(None),) + mid].numpy(), float(to[mid])
         e = max(abs(rg - ro) / abs(ro), np.max(np.abs(ug - uo)) / 0.1, abs(tg - to) / T0)
         worst = max(worst, e)
     _say("worst sampled error", worst)

@@ -1,0 +1,147 @@
+"""The shock tube of the results section on the GPU: end planes held at the
+equilibria of C_L and C_R (lbm_set_fixed_planes), sides periodic.  Parity
+with the oracle element by element on tubes whose waves reach the held
+planes, and the paper-size 11 x 11 x 800 tube against the oracle and the
+exact Riemann plateaus."""
+import numpy as np
+import pytest
+import torch
+
+from gpu_helpers import new_sim, rel_errors
+from oracle import equilibrium as oeq, lbm as olbm, riemann as orm, velocity_sets as ovs
+from paper_1303_4624_amd import _lib as L
+from synth_inputs import WORKLOADS, smooth_ic, tube_ic, tube_states, workload_ic
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-12
+FP32S_TOL = 1e-5
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _state(rho, theta, T0, D, u=0.0):
+    return (rho,) + (u,) * D + (theta * T0,)
+
+
+def _gpu(model, extent, omega, rho, U, th, steps, hold, precision="fp64"):
+    sim = new_sim(model, extent, omega, precision)
+    n_lo, n_hi, lo, hi = hold(sim.T0)
+    sim.init_fields(rho, U, th * sim.T0)
+    sim.set_fixed_planes(n_lo, n_hi, lo, hi)
+    sim.step(steps)
+    r, u, t = [x.cpu().numpy() for x in sim.moments()]
+    f = sim.get_populations().cpu()
+    T0 = sim.T0
+    sim.close()
+    return r, u, t, T0, f
+
+
+def _oracle(model, rho, U, th, steps, omega, hold):
+    v = ovs.velocity_set(model)
+    f = olbm.run(v, olbm.init_populations(v, rho, U, th * v.T0), omega, steps, hold(v.T0))
+    r, u, t = oeq.moments(v, f)
+    return r.numpy(), u.numpy(), t.numpy(), f, v
+
+
+@pytest.mark.parametrize("model,extent,steps,n_lo,n_hi", [
+    # waves from the centre reach and reflect off the held planes
+    ("D3Q95", (5, 3, 40), 30, 5, 5),
+    ("D3Q95", (7, 2, 33), 25, 5, 2),     # asymmetric, thinner than the stencil at the top
+    ("D3Q95", (300, 2, 24), 10, 0, 5),   # one held end; rows span two chunks, ragged tail
+    ("D2Q33", (7, 33), 30, 4, 4),
+    ("D2Q33", (5, 28), 20, 3, 0),
+])
+def test_held_tube_matches_oracle_elementwise(model, extent, steps, n_lo, n_hi):
+    _say("case", model, extent, steps, n_lo, n_hi)
+    D = len(extent)
+    rho, U, th = tube_ic(extent, extent[-1] // 2, (2.0, 1.0), (1.0, 1.1))
+    # a smooth perturbation so that no two nodes of a plane agree
+    pr, pU, pth = smooth_ic(extent, seeds=(71, 72, 73, 74, 75), amp_u=0.02, amp_rho=0.02,
+                            amp_theta=0.02)
+    rho, U, th = rho * pr, U + pU, th * pth
+
+    def hold(T0):
+        return (n_lo, n_hi, _state(2.0, 1.0, T0, D), _state(1.0, 1.1, T0, D, 0.01))
+
+    r, u, t, T0, f = _gpu(model, extent, 1.4, rho, U, th, steps, hold)
+    ro, uo, to, fo, v = _oracle(model, rho, U, th, steps, 1.4, hold)
+    er, eu, et = rel_errors((r, u, t), (ro, uo, to), T0)
+    want = olbm.collide(v, fo, 1.4)    # the library stores post-collision populations
+    ef = float(torch.max(torch.abs(f - want)) / torch.max(torch.abs(want)))
+    _say("errors", er, eu, et, ef)
+    assert max(er, eu, et, ef) <= FP64_TOL
+    r32, u32, t32, _, _ = _gpu(model, extent, 1.4, rho, U, th, steps, hold, "fp32s")
+    e32 = rel_errors((r32, u32, t32), (ro, uo, to), T0)
+    _say("fp32s errors", *e32)
+    assert max(e32) <= FP32S_TOL
+
+
+@pytest.mark.parametrize("wname,plateaus", [
+    ("d3q95_11x11x800_tube", ((300, 480), (540, 700))),
+    ("d2q33_11x800_tube", ((340, 390), (470, 580))),
+])
+@pytest.mark.parametrize("precision,tol", [("fp64", FP64_TOL), ("fp32s", FP32S_TOL)])
+def test_paper_tube_matches_oracle_and_exact_plateaus(wname, plateaus, precision, tol):
+    # The sides are periodic and the initial state is uniform across them, so
+    # the oracle's one-node-wide tube is the exact answer for every node of a
+    # plane; the GPU must also keep every plane uniform.
+    w = WORKLOADS[wname]
+    _say("case", wname, precision, w.extent, w.steps)
+    D = len(w.extent)
+    (lr, lt), (rr, rt) = tube_states(w)
+    nh = int(w.extra["hold"])
+
+    def hold(T0):
+        return (nh, nh, _state(lr, lt, T0, D), _state(rr, rt, T0, D))
+
+    rho, U, th = workload_ic(w)
+    r, u, t, T0, _ = _gpu(w.model, w.extent, w.omega, rho, U, th, w.steps, hold, precision)
+    ext1 = (1,) * (D - 1) + (w.extent[-1],)
+    r1, U1, th1 = workload_ic(w, ext1)
+    ro, uo, to, _, v = _oracle(w.model, r1, U1, th1, w.steps, w.omega, hold)
+    axes = tuple(range(1, D))
+    for a, b in ((r, ro), (t, to)):
+        assert np.all(a == a[(slice(None),) + (slice(0, 1),) * (D - 1)]), "plane not uniform"
+    er, eu, et = rel_errors((r, u, t), (np.broadcast_to(ro, r.shape),
+                                        np.broadcast_to(uo, u.shape),
+                                        np.broadcast_to(to, t.shape)), T0)
+    _say("errors", er, eu, et)
+    assert max(er, eu, et) <= tol
+    st = orm.star_state((lr, 0.0, lr * lt * T0), (rr, 0.0, rr * rt * T0),
+                        orm.monatomic_gamma(D))
+    rz = r.mean(axis=axes)
+    tz = t.mean(axis=axes)
+    (a, b), (c, d) = plateaus
+    dev = (rz[a:b].mean() / st.rho_l - 1, rz[c:d].mean() / st.rho_r - 1,
+           tz[a:b].mean() / (st.p / st.rho_l) - 1, tz[c:d].mean() / (st.p / st.rho_r) - 1)
+    _say("plateau deviations", dev)
+    assert max(abs(x) for x in dev) < 2e-3
+
+
+def test_held_planes_refuse_checkpoints_and_clear_to_periodic():
+    ext = (6, 4, 20)
+    rho, U, th = smooth_ic(ext, seeds=(81, 82, 83, 84, 85), amp_u=0.03)
+    sim = new_sim("D3Q95", ext, 1.3)
+    ref = new_sim("D3Q95", ext, 1.3)
+    try:
+        st = _state(1.0, 1.0, sim.T0, 3)
+        sim.init_fields(rho, U, th * sim.T0)
+        sim.set_fixed_planes(5, 5, st, st)
+        with pytest.raises(L.LBMError) as ex:
+            sim.run_checkpointed(4, 2)
+        assert ex.value.status == L.LBM_E_UNSUPPORTED
+        ck = torch.zeros(8, dtype=torch.float64, device="cuda")
+        with pytest.raises(L.LBMError) as ex:
+            sim.adjoint(4, 2, ck, rho, U, th * sim.T0, np.ones_like(rho))
+        assert ex.value.status == L.LBM_E_UNSUPPORTED
+        sim.set_fixed_planes(0, 0)
+        sim.step(7)
+        ref.init_fields(rho, U, th * ref.T0)
+        ref.step(7)
+        assert torch.equal(sim.get_populations(), ref.get_populations())
+    finally:
+        sim.close()
+        ref.close()

@@ -10,7 +10,7 @@ import torch
 
 from conftest import read_golden
 from oracle import equilibrium as eq, lbm, riemann as rm, velocity_sets as vs
-from synth_inputs import WORKLOADS, grid_shape, smooth_ic, workload_ic
+from synth_inputs import WORKLOADS, grid_shape, smooth_ic, tube_ic, tube_states, workload_ic
 
 MODELS = ["D2Q33", "D3Q95"]
 
@@ -227,3 +227,95 @@ def test_adjoint_pairing_is_invariant_in_time():
     pairs = [float((f.grad * f.detach()).sum()) for f in fs]
     scale = max(float((f.grad * f.detach()).abs().sum()) for f in fs)
     assert max(abs(p - pairs[-1]) for p in pairs) <= 1e-13 * scale
+
+
+# -- the shock tube with end planes held at C_L and C_R (results section) ----
+
+def _tube_hold(w, T0, n=None):
+    (lr, lt), (rr, rt) = tube_states(w)
+    D = len(w.extent)
+    n = int(w.extra["hold"]) if n is None else n
+    return (n, n, (lr,) + (0.0,) * D + (lt * T0,), (rr,) + (0.0,) * D + (rt * T0,))
+
+
+@pytest.mark.parametrize("wname,plateaus", [
+    # (start, stop) of the left and right plateaus at t = 120, between the
+    # rarefaction tail, the contact and the shock of the exact solution
+    ("d3q95_11x11x800_tube", ((300, 480), (540, 700))),
+    ("d2q33_11x800_tube", ((340, 390), (470, 580))),
+])
+def test_tube_with_held_end_planes_reaches_exact_riemann_plateaus(wname, plateaus):
+    # The experiment's claim: density and temperature agree with the exact
+    # solution of the Riemann problem on the plateaus.  The sides are periodic
+    # and the initial state is uniform across them, so one node per plane
+    # represents the 11-wide tube exactly.
+    w = WORKLOADS[wname]
+    v = vs.velocity_set(w.model)
+    ext = (1,) * (len(w.extent) - 1) + (w.extent[-1],)
+    rho, U, th = workload_ic(w, ext)
+    f = lbm.run(v, lbm.init_populations(v, rho, U, th * v.T0), w.omega, w.steps,
+                _tube_hold(w, v.T0))
+    r, u, T = eq.moments(v, f)
+    r = r.reshape(-1).numpy()
+    T = T.reshape(-1).numpy()
+    uz = u[-1].reshape(-1).numpy()
+    (lr, lt), (rr, rt) = tube_states(w)
+    st = rm.star_state((lr, 0.0, lr * lt * v.T0), (rr, 0.0, rr * rt * v.T0),
+                       rm.monatomic_gamma(v.D))
+    (a, b), (c, d) = plateaus
+    assert abs(r[a:b].mean() / st.rho_l - 1) < 2e-3
+    assert abs(r[c:d].mean() / st.rho_r - 1) < 2e-3
+    assert abs(T[a:b].mean() / (st.p / st.rho_l) - 1) < 2e-3
+    assert abs(T[c:d].mean() / (st.p / st.rho_r) - 1) < 2e-3
+    assert abs(uz[a:d].mean() / st.u - 1) < 2e-3
+    # undisturbed ends: the held planes and their neighbours keep C_L / C_R
+    assert np.allclose(r[:20], lr, rtol=1e-12) and np.allclose(r[-20:], rr, rtol=1e-12)
+
+
+@pytest.mark.parametrize("name", MODELS)
+def test_held_planes_close_the_periodic_seam(name):
+    # Nodes gather from at most m = max|e_z| planes away.  With m planes held
+    # at each end, what the far end holds reaches a node only through the
+    # interior, at most m planes per step: after t steps nodes below
+    # L - m - m t are identical for two different far-end states.  Holding
+    # fewer planes lets the far end in through the seam at once.
+    v = vs.velocity_set(name)
+    m = int(np.abs(v.e[:, -1]).max())
+    L = 60
+    ext = (3,) * (v.D - 1) + (L,)
+    rho, U, th = tube_ic(ext, L // 2, (2.0, 1.0), (1.0, 1.2))
+    f0 = lbm.init_populations(v, rho, U, th * v.T0)
+    lo = (2.0,) + (0.0,) * v.D + (v.T0,)
+    hi_a = (1.0,) + (0.0,) * v.D + (1.2 * v.T0,)
+    hi_b = (0.7,) + (0.05,) * v.D + (0.9 * v.T0,)
+    for t in (1, 3, 5):
+        fa = lbm.run(v, f0, 1.3, t, (m, m, lo, hi_a))
+        fb = lbm.run(v, f0, 1.3, t, (m, m, lo, hi_b))
+        cut = L - m - m * t
+        assert torch.equal(fa[:, :cut], fb[:, :cut])
+        assert not torch.equal(fa[:, cut:], fb[:, cut:])
+        # the held planes carry f^eq of the held states
+        ra, ua, Ta = eq.moments(v, fa)
+        assert torch.allclose(ra[:m], torch.full_like(ra[:m], 2.0), rtol=1e-14)
+        assert torch.allclose(Ta[-m:], torch.full_like(Ta[-m:], 1.2 * v.T0), rtol=1e-14)
+    # the second step gathers the first step's held planes across the seam
+    fa = lbm.run(v, f0, 1.3, 2, (m - 1, m - 1, lo, hi_a))
+    fb = lbm.run(v, f0, 1.3, 2, (m - 1, m - 1, lo, hi_b))
+    assert not torch.equal(fa[:, m - 1], fb[:, m - 1])
+
+
+def test_held_planes_of_the_periodic_state_change_nothing():
+    # Holding both ends at the state a uniform lattice already has is the
+    # periodic run; holding zero planes is the periodic run for any state.
+    v = vs.velocity_set("D2Q33")
+    ext = (4, 30)
+    shape = grid_shape(ext)
+    st = (1.3, 0.02, -0.01, 0.9 * v.T0)
+    f0 = lbm.init_populations(v, np.full(shape, st[0]),
+                              np.stack([np.full(shape, st[1]), np.full(shape, st[2])]),
+                              np.full(shape, st[3]))
+    fp = lbm.run(v, f0, 1.1, 4)
+    assert torch.allclose(lbm.run(v, f0, 1.1, 4, (4, 4, st, st)), fp, rtol=0, atol=1e-15)
+    rho, U, th = smooth_ic(ext, seeds=(61, 62, 63, 64), amp_u=0.03)
+    f1 = lbm.init_populations(v, rho, U, th * v.T0)
+    assert torch.equal(lbm.run(v, f1, 1.1, 4, (0, 0, None, None)), lbm.run(v, f1, 1.1, 4))
