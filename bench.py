@@ -87,9 +87,9 @@ def run_headline(extent, omega, steps, warmup):
     return wall, ev, ok, cons
 
 
-def run_fp64_and_error(extent, omega, steps_time, steps_err):
-    """FP64 throughput on `extent`, and the FP32-shifted vs FP64 GPU error
-    after `steps_err` steps from the same initial fields."""
+def run_fp64_and_error(extent, omega, steps_time, steps_err, model="D3Q95"):
+    """FP64 and FP32-shifted throughput on `extent`, and the FP32-shifted vs
+    FP64 GPU error after `steps_err` steps from the same initial fields."""
     import torch
     from paper_1303_4624_amd import Simulation
     from synth_inputs import smooth_ic
@@ -97,7 +97,7 @@ def run_fp64_and_error(extent, omega, steps_time, steps_err):
     out = {}
     fields = {}
     for prec in ("fp64", "fp32s"):
-        sim = Simulation("D3Q95", extent, omega, precision=prec)
+        sim = Simulation(model, extent, omega, precision=prec)
         sim.init_fields(rho, U, th * sim.T0)
         sim.step(steps_err)
         fields[prec] = [x.clone() for x in sim.moments()]
@@ -118,6 +118,28 @@ def run_fp64_and_error(extent, omega, steps_time, steps_err):
     del fields
     torch.cuda.empty_cache()
     return out, err
+
+
+def run_tube(wname, precision):
+    """The shock tube with held end planes: time its whole run."""
+    import torch
+    from paper_1303_4624_amd import Simulation
+    from synth_inputs import WORKLOADS, tube_states, workload_ic
+    w = WORKLOADS[wname]
+    D = len(w.extent)
+    (lr, lt), (rr, rt) = tube_states(w)
+    rho, U, th = workload_ic(w)
+    sim = Simulation(w.model, w.extent, w.omega, precision=precision)
+    sim.init_fields(rho, U, th * sim.T0)
+    nh = int(w.extra["hold"])
+    sim.set_fixed_planes(nh, nh, (lr,) + (0.0,) * D + (lt * sim.T0,),
+                         (rr,) + (0.0,) * D + (rt * sim.T0,))
+    wall, ev = timed_steps(sim, w.steps, 0)
+    N = sim.N
+    sim.close()
+    torch.cuda.empty_cache()
+    return {"steps": w.steps, "ms_per_step": round(ev / w.steps * 1e3, 4),
+            "mlups": round(N * w.steps / ev / 1e6, 2)}
 
 
 def run_fwd_adjoint(extent, omega, n, k, keep=1):
@@ -291,6 +313,17 @@ def main():
         out["fp64_256c"]["roofline_frac"] = round(
             out["fp64_256c"]["mlups"] * 1520 / 1e3 / HBM_PEAK_GBS, 4)
         out["fp32s_vs_fp64_256c"] = err
+        log("[bench] D2Q33 fp64 vs fp32s on 8192^2")
+        thr, err = run_fp64_and_error((8192, 8192), 1.5, 100, 200, model="D2Q33")
+        for prec, bpc in (("fp64", 528), ("fp32s", 264)):
+            d = {k: round(v, 3) for k, v in thr[prec].items()}
+            d["roofline_frac"] = round(d["mlups"] * bpc / 1e3 / HBM_PEAK_GBS, 4)
+            out[f"d2q33_{prec}_8192sq"] = d
+        out["d2q33_fp32s_vs_fp64_8192sq"] = err
+        log("[bench] shock tubes with held end planes")
+        for wname in ("d3q95_11x11x800_tube", "d2q33_11x800_tube"):
+            for prec in ("fp64", "fp32s"):
+                out[f"{wname}_{prec}"] = run_tube(wname, prec)
         log("[bench] forward + adjoint on 128^3")
         out["fwd_adjoint_128c"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20, keep=1)
         out["fwd_adjoint_128c_all_moments_kept"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20,

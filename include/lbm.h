@@ -185,6 +185,30 @@ int lbm_moments(lbm_ctx* ctx, double* rho, double* U, double* T);
  */
 int lbm_conservation(lbm_ctx* ctx, double* out);
 
+/*
+ * lbm_set_fixed_planes - the shock-tube end conditions of the experiment in
+ * the results section: the first n_lo and the last n_hi planes along the
+ * slowest axis (the XY-planes at the two ends of z in 3D, the X-rows at the
+ * two ends of y in 2D) are held at the equilibrium f^eq(state) of a fixed
+ * macroscopic state; the other axes stay periodic.
+ *   state_lo, state_hi : host double[D+2] = {rho, U_x, U_y[, U_z], T}
+ *                        (rho > 0, T > 0, finite); read during the call
+ *                        and copied; may be NULL where the count is 0.
+ * After every subsequent update step of lbm_step the held planes are
+ * overwritten with f^eq(state), which the collision leaves unchanged, so
+ * they act as reservoirs.  The populations a cell gathers come from at most
+ * max|e_z| planes away (5 for D3Q95, 4 for D2Q33 along y): with
+ * n_lo, n_hi >= that, no interior cell gathers across the periodic seam.
+ * The held planes are not touched until the next step (set the initial
+ * state with lbm_init_fields).  n_lo = n_hi = 0 restores a fully periodic
+ * lattice.  Returns LBM_E_INVALID for n_lo, n_hi < 0, n_lo + n_hi >
+ * extent[D-1], NULL or non-positive states, LBM_E_NONFINITE for NaN/Inf.
+ * lbm_run_checkpointed and lbm_adjoint return LBM_E_UNSUPPORTED while
+ * planes are held.
+ */
+int lbm_set_fixed_planes(lbm_ctx* ctx, int n_lo, int n_hi, const double* state_lo,
+                         const double* state_hi);
+
 /* lbm_set_omega - change the relaxation frequency (0 <= omega < 2). */
 int lbm_set_omega(lbm_ctx* ctx, double omega);
 

@@ -30,7 +30,7 @@ LBM_MAX_Q = 95
 EXPORTED = [
     "lbm_velocity_set", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments",
-    "lbm_conservation", "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
+    "lbm_conservation", "lbm_set_fixed_planes", "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_str",
     "lbm_last_error",
 ]
@@ -63,6 +63,7 @@ _SIGS = {
     "lbm_step": (_c.c_int, [_vp, _c.c_int]),
     "lbm_moments": (_c.c_int, [_vp, _vp, _vp, _vp]),
     "lbm_conservation": (_c.c_int, [_vp, _pd]),
+    "lbm_set_fixed_planes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _pd, _pd]),
     "lbm_set_omega": (_c.c_int, [_vp, _c.c_double]),
     "lbm_checkpoint_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _psz]),
     "lbm_run_checkpointed": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _vp, _sz]),
@@ -180,6 +181,16 @@ def lbm_conservation(ctx, D: int) -> np.ndarray:
     out = np.zeros(D + 2, dtype=np.float64)
     _check(library().lbm_conservation(ctx, out.ctypes.data_as(_pd)), "lbm_conservation", ctx)
     return out
+
+
+def lbm_set_fixed_planes(ctx, n_lo: int, n_hi: int, state_lo=None, state_hi=None) -> None:
+    """state_* : sequences (rho, U_x, U_y[, U_z], T) or None where the count is 0."""
+    def arr(s):
+        return None if s is None else np.ascontiguousarray(s, dtype=np.float64)
+    lo, hi = arr(state_lo), arr(state_hi)
+    _check(library().lbm_set_fixed_planes(
+        ctx, int(n_lo), int(n_hi), None if lo is None else lo.ctypes.data_as(_pd),
+        None if hi is None else hi.ctypes.data_as(_pd)), "lbm_set_fixed_planes", ctx)
 
 
 def lbm_set_omega(ctx, omega: float) -> None:

@@ -39,6 +39,8 @@ struct lbm_ctx {
     bool bound = false;
     bool initialized = false;
     KParams kp{};
+    int hold_lo = 0, hold_hi = 0;   // planes held at f^eq at each end of the slowest axis
+    lbm::FixedState hold[2]{};
     std::string err;
 };
 
@@ -361,8 +363,43 @@ LBM_API int lbm_step(lbm_ctx* ctx, int n) {
         hipError_t e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
                                         ctx->f[1 - ctx->cur], nullptr, ctx->stream);
         if (e != hipSuccess) return fail_hip(ctx, e, "step kernel");
+        if (ctx->hold_lo + ctx->hold_hi > 0) {
+            e = lbm::launch_fix_planes(ctx->model, ctx->prec, ctx->kp, ctx->f[1 - ctx->cur],
+                                       ctx->N / ctx->extent[ctx->D - 1], ctx->hold_lo,
+                                       ctx->hold_hi, static_cast<int>(ctx->extent[ctx->D - 1]),
+                                       ctx->hold[0], ctx->hold[1], ctx->stream);
+            if (e != hipSuccess) return fail_hip(ctx, e, "fixed-plane kernel");
+        }
         ctx->cur = 1 - ctx->cur;
     }
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_fixed_planes(lbm_ctx* ctx, int n_lo, int n_hi, const double* state_lo,
+                                 const double* state_hi) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    const int64_t L = ctx->extent[ctx->D - 1];
+    if (n_lo < 0 || n_hi < 0 || static_cast<int64_t>(n_lo) + n_hi > L)
+        return fail(ctx, LBM_E_INVALID, "need n_lo, n_hi >= 0 and n_lo + n_hi <= extent[D-1]");
+    const double* st[2] = {state_lo, state_hi};
+    const int cnt[2] = {n_lo, n_hi};
+    lbm::FixedState fs[2]{};
+    for (int s = 0; s < 2; ++s) {
+        if (cnt[s] == 0) continue;
+        if (!st[s]) return fail(ctx, LBM_E_INVALID, "state of a held end is NULL");
+        for (int j = 0; j < ctx->D + 2; ++j)
+            if (!std::isfinite(st[s][j]))
+                return fail(ctx, LBM_E_NONFINITE, "held state has a non-finite value");
+        if (!(st[s][0] > 0.0) || !(st[s][ctx->D + 1] > 0.0))
+            return fail(ctx, LBM_E_INVALID, "held state needs rho > 0 and T > 0");
+        fs[s].rho = st[s][0];
+        for (int a = 0; a < ctx->D; ++a) fs[s].U[a] = st[s][1 + a];
+        fs[s].T = st[s][ctx->D + 1];
+    }
+    ctx->hold_lo = n_lo;
+    ctx->hold_hi = n_hi;
+    ctx->hold[0] = fs[0];
+    ctx->hold[1] = fs[1];
     return LBM_OK;
 }
 
@@ -474,6 +511,9 @@ LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckp
     int rc;
     if ((rc = require_init(ctx)) != LBM_OK) return rc;
     if (n < 1 || k < 1 || keep < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
+    if (ctx->hold_lo + ctx->hold_hi > 0)
+        return fail(ctx, LBM_E_UNSUPPORTED, "checkpointed runs need an all-periodic lattice "
+                                            "(fixed planes are set)");
     const CkLayout c = ck_layout(ctx, n, k, keep);
     if (ckpt_bytes < c.total) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
     if ((rc = check_dev(ctx, ckpt, c.total, "ckpt")) != LBM_OK) return rc;
@@ -549,6 +589,9 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
     if (!ctx->bound) return fail(ctx, LBM_E_STATE, "no buffers bound (call lbm_bind)");
     if (n < 1 || k < 1 || keep < 1)
         return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
+    if (ctx->hold_lo + ctx->hold_hi > 0)
+        return fail(ctx, LBM_E_UNSUPPORTED, "the adjoint needs an all-periodic lattice "
+                                            "(fixed planes are set)");
     if (dL_domega && std::fabs(1.0 - ctx->omega) < 1e-3)
         return fail(ctx, LBM_E_INVALID,
                     "the omega gradient needs |1 - omega| >= 1e-3 (it is divided by 1 - omega)");

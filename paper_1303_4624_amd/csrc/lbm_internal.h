@@ -40,6 +40,13 @@ struct KParams {
     double K1[kMaxG], K2[kMaxG], K3[kMaxG], K4[kMaxG], K5[kMaxG];
 };
 
+// A macroscopic state held fixed on boundary planes.
+struct FixedState {
+    double rho;
+    double U[3];
+    double T;
+};
+
 // Launch geometry of the row-blocked kernels: one grid row (fixed y, z) is
 // split into `chunks` blocks of `bx` threads.
 struct RowLaunch {
@@ -59,6 +66,9 @@ constexpr int kReduceThreads = 256;
 // Launchers: each returns the hipError_t of the launch.
 hipError_t launch_init(ModelId m, Prec p, const KParams& kp, const double* rho, const double* U,
                        const double* T, void* f, hipStream_t s);
+hipError_t launch_fix_planes(ModelId m, Prec p, const KParams& kp, void* f, long long plane,
+                             int n_lo, int n_hi, int nlast, const FixedState& lo,
+                             const FixedState& hi, hipStream_t s);
 hipError_t launch_set_pop(ModelId m, Prec p, const KParams& kp, const double* fin, void* f,
                           hipStream_t s);
 hipError_t launch_get_pop(ModelId m, Prec p, const KParams& kp, const void* f, double* fout,

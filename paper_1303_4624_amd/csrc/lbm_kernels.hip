@@ -58,6 +58,9 @@ namespace {
 #ifndef LBM_F32_WAVES
 #define LBM_F32_WAVES 1
 #endif
+#ifndef LBM_F32S_SUM64
+#define LBM_F32S_SUM64 1
+#endif
 constexpr int kBlock = 256;            // threads per block of the cell-parallel kernels
 constexpr int kStepMaxB = LBM_STEP_MAXB;  // largest block of the row-blocked kernels
 constexpr int kW = 2 * kMaxDisp + 1;   // distinct displacement components
@@ -73,12 +76,21 @@ __device__ __forceinline__ void static_for(F&& f) {
 
 struct F64T {
     using S = double;
+    using Acc = double;   // type of the per-cell moment sums
     static constexpr bool shifted = false;
     static constexpr int waves = 1;
     static constexpr int adj_waves = 1;
 };
 struct F32ST {
     using S = float;
+    // Moment sums of the float32 deviations in float64: a float32 sum of 95
+    // terms is off by a few ulps of sum |e|^2 |g|, the same in every node of
+    // a uniform region, so without it such regions drift coherently.
+#if LBM_F32S_SUM64
+    using Acc = double;
+#else
+    using Acc = float;
+#endif
     static constexpr bool shifted = true;
     static constexpr int waves = LBM_F32_WAVES;
     static constexpr int adj_waves = LBM_ADJ_WAVES;
@@ -301,16 +313,18 @@ void k_step(const typename P::S* __restrict__ src,
     S v[Q];
     gather<M, +1>(src, k, cl, v);
 
-    R m0 = R(0), jx = R(0), jy = R(0), jz = R(0), en = R(0);
+    using A = typename P::Acc;
+    A m0 = A(0), jx = A(0), jy = A(0), jz = A(0), en = A(0);
     static_for<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
         constexpr int ee = M::table.e2[M::table.group[i]];
-        m0 += v[i];
-        if constexpr (ex != 0) jx += R(ex) * v[i];
-        if constexpr (ey != 0) jy += R(ey) * v[i];
-        if constexpr (ez != 0) jz += R(ez) * v[i];
-        if constexpr (ee != 0) en += R(ee) * v[i];
+        const A vi = A(v[i]);
+        m0 += vi;
+        if constexpr (ex != 0) jx += A(ex) * vi;
+        if constexpr (ey != 0) jy += A(ey) * vi;
+        if constexpr (ez != 0) jz += A(ez) * vi;
+        if constexpr (ee != 0) en += A(ee) * vi;
     });
 
     const Macro mc = macro_from_sums<D, P::shifted>(k, m0, jx, jy, jz, en);
@@ -353,22 +367,15 @@ void k_step(const typename P::S* __restrict__ src,
 }
 
 // ---------------------------------------------------------------------------
-// f = f^eq(rho, U, T) from float64 fields, computed in float64.
+// Store f^eq(r, U, T) of one cell, computed in float64 (Formula (3)).
 template <class M, class P>
-__global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ rho,
-                                                 const double* __restrict__ U,
-                                                 const double* __restrict__ T,
-                                                 typename P::S* __restrict__ f, KParams k) {
-    constexpr int D = M::D;
-    constexpr int G = M::G;
-    const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (c >= k.N) return;
-    const double r = rho[c];
-    const double ux = U[c], uy = U[k.N + c], uz = (D == 3) ? U[2 * k.N + c] : 0.0;
-    const double d = T[c] * k.invT0 - 1.0;
+__device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const KParams& k,
+                                          long long c, double r, double ux, double uy,
+                                          double uz, double T) {
+    const double d = T * k.invT0 - 1.0;
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
-    static_for<G>([&](auto GI) {
+    static_for<M::G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
         const GCoef gc = group_coef(k, g, u2, d);
         const double w = k.W[g];
@@ -384,6 +391,34 @@ __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ rho,
             }
         });
     });
+}
+
+// f = f^eq(rho, U, T) from float64 fields.
+template <class M, class P>
+__global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ rho,
+                                                 const double* __restrict__ U,
+                                                 const double* __restrict__ T,
+                                                 typename P::S* __restrict__ f, KParams k) {
+    const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= k.N) return;
+    store_feq<M, P>(f, k, c, rho[c], U[c], U[k.N + c], (M::D == 3) ? U[2 * k.N + c] : 0.0, T[c]);
+}
+
+// Hold the first n_lo and the last n_hi planes of the slowest axis at the
+// equilibrium of fixed states: f* = f^eq(lo) resp. f^eq(hi) there.  One
+// thread per cell of those planes; `plane` = cells per plane, `nlast` =
+// planes along the slowest axis.
+template <class M, class P>
+__global__ __launch_bounds__(kBlock) void k_fix_planes(typename P::S* __restrict__ f, KParams k,
+                                                       long long plane, int n_lo, int n_hi,
+                                                       int nlast, FixedState lo, FixedState hi) {
+    const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const long long cells_lo = plane * n_lo;
+    if (t >= plane * (n_lo + n_hi)) return;
+    const bool is_lo = t < cells_lo;
+    const long long c = is_lo ? t : static_cast<long long>(nlast - n_hi) * plane + (t - cells_lo);
+    const FixedState& st = is_lo ? lo : hi;
+    store_feq<M, P>(f, k, c, st.rho, st.U[0], st.U[1], st.U[2], st.T);
 }
 
 // Copy float64 f[Q][N] into storage, and back.
@@ -754,6 +789,20 @@ hipError_t launch_init(ModelId m, Prec p, const KParams& kp, const double* rho, 
         using P = decltype(P_);
         hipLaunchKernelGGL((k_init<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s, rho, U, T,
                            static_cast<typename P::S*>(f), kp);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_fix_planes(ModelId m, Prec p, const KParams& kp, void* f, long long plane,
+                             int n_lo, int n_hi, int nlast, const FixedState& lo,
+                             const FixedState& hi, hipStream_t s) {
+    const long long cells = plane * (n_lo + n_hi);
+    if (cells <= 0) return hipSuccess;
+    return with_types(m, p, [&](auto M_, auto P_) {
+        using M = decltype(M_);
+        using P = decltype(P_);
+        hipLaunchKernelGGL((k_fix_planes<M, P>), dim3(cell_blocks(cells)), dim3(kBlock), 0, s,
+                           static_cast<typename P::S*>(f), kp, plane, n_lo, n_hi, nlast, lo, hi);
         return hipGetLastError();
     });
 }

@@ -102,6 +102,14 @@ class Simulation:
     def conservation(self) -> np.ndarray:
         return L.lbm_conservation(self.ctx, self.D)
 
+    def set_fixed_planes(self, n_lo: int, n_hi: int, state_lo=None, state_hi=None) -> None:
+        """Hold the first n_lo / last n_hi planes of the slowest axis at
+        f^eq(state) after every step; a state is (rho, U_x, U_y[, U_z], T)."""
+        for s, n in ((state_lo, n_lo), (state_hi, n_hi)):
+            if n and (s is None or len(s) != self.D + 2):
+                raise ValueError(f"a held state needs D + 2 = {self.D + 2} values")
+        L.lbm_set_fixed_planes(self.ctx, n_lo, n_hi, state_lo, state_hi)
+
     def set_omega(self, omega: float) -> None:
         L.lbm_set_omega(self.ctx, omega)
         self.omega = float(omega)
