@@ -6,10 +6,12 @@ Headline: D3Q95 FP32-shifted, 384^3 periodic grid, omega = 1.8, seeded smooth
 random initial fields; K timed update steps (one stream-collide kernel per
 step) after W warm-up steps.  Prints ONE JSON line with MLUPS, the roofline
 of the dominant kernel (algorithmic bytes 2 Q 4 = 760 B per cell update over
-the HIP-event duration of the timed launches, against 8 TB/s HBM), the CPU
-oracle's rate on a bounded sample, and side measurements: FP64 on 256^3,
-FP32-shifted vs FP64 error after 200 steps on 256^3, and the forward +
-adjoint cost on 128^3 x 200 steps with checkpoints every 20.
+the HIP-event duration of the timed launches, against 8 TB/s HBM; the HBM
+bytes per launch measured by rocprofv3 counters on the same kernel source),
+the CPU oracle's rate on a bounded sample, and side measurements: FP64 on
+256^3, FP32-shifted vs FP64 error after 200 steps on 256^3, D2Q33 in both
+precisions on 8192^2, the two shock tubes with held end planes, and the
+forward + adjoint cost on 128^3 x 200 steps with checkpoints every 20.
 """
 from __future__ import annotations
 
@@ -276,7 +278,7 @@ def main():
     per_launch_s = ev / args.steps
     bytes_per_launch = 2 * Q * 4 * N
     achieved = bytes_per_launch / per_launch_s / 1e9
-    traffic = measured_traffic()
+    traffic = measured_traffic() if args.grid == 384 else None
     log(f"[bench] {mlups:.1f} MLUPS, {achieved:.1f} GB/s, wall {wall:.3f}s events {ev:.3f}s")
 
     out = {
@@ -298,7 +300,10 @@ def main():
                    "cell_updates_per_step": N},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic},
+                     "traffic": traffic, "traffic_unit": "B per launch (rocprofv3 FETCH_SIZE + "
+                     "WRITE_SIZE, calibrated on a device copy)",
+                     "traffic_over_algorithmic": (round(traffic / bytes_per_launch, 4)
+                                                  if traffic else None)},
         "finite": ok,
         "mass_after": cons[0],
     }
