@@ -24,9 +24,14 @@
  *    lbm_last_error() describes the failure.
  *  - Grid: extents (nx, ny[, nz]), every axis periodic, N = nx*ny[*nz] cells,
  *    linear cell index x + nx*(y + ny*z) (x fastest).
- *  - Populations: structure of arrays, value of population i at cell c at
- *    element i*N + c.  In LBM_FP64 each element is the double f*_i.  In
- *    LBM_FP32_SHIFTED each element is the float g_i = f*_i - w_i*rho0.
+ *  - Populations in the bound buffers, checkpoints and adjoint workspace:
+ *    row-blocked, i.e. the Q populations of one grid row (fixed y[, z]) are
+ *    contiguous and population-major inside the row: population i of cell
+ *    c = x + nx*r (r = y + ny*z the row) is element (r*Q + i)*nx + x.  In
+ *    LBM_FP64 each element is the double f*_i.  In LBM_FP32_SHIFTED each
+ *    element is the float g_i = f*_i - w_i*rho0.  lbm_set_populations and
+ *    lbm_get_populations exchange float64 f* in the order [Q][N] (element
+ *    i*N + c) instead.
  *  - Stored state: the post-collision populations
  *    f*_i(x, t) = (1 - omega) f_i(x, t) + omega f_i^eq(x, t), i.e. the
  *    right-hand side of the update rule; the next step moves them to x + e_i,
@@ -110,8 +115,9 @@ int lbm_velocity_set(int D, int Q, int32_t* e, double* w, double* c);
  *               summing to 1 within 1e-12.
  *   c         : speed of the model; Formula (5) must hold at (w, c) with
  *               residual <= 1e-10, else LBM_E_INVALID.
- *   extent    : host int64[D] = {nx, ny[, nz]}, each >= 1; N*Q must fit
- *               in int64 and nx <= 2^24.
+ *   extent    : host int64[D] = {nx, ny[, nz]}, each >= 1 and <= 2^24; the
+ *               populations of one slab of the slowest axis (nx*ny*Q
+ *               elements in 3D, nx*Q in 2D) must stay below 4 GiB.
  *   omega     : relaxation frequency of the update rule, 0 <= omega < 2.
  *               (omega = 0 turns the update into pure streaming.)
  *   precision : LBM_FP64 or LBM_FP32_SHIFTED.

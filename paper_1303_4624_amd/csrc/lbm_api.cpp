@@ -66,11 +66,8 @@ int fail_hip(lbm_ctx* ctx, hipError_t e, const char* what) {
 
 size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
-// Elements between two population planes of the stored state.
-long long plane_stride(const lbm_ctx* ctx) { return ctx->N + lbm::kPlanePad; }
-
 size_t pop_bytes(const lbm_ctx* ctx) {
-    return static_cast<size_t>(plane_stride(ctx)) * ctx->Q * elem_bytes(ctx->prec);
+    return static_cast<size_t>(ctx->N) * ctx->Q * elem_bytes(ctx->prec);
 }
 
 size_t scratch_bytes(const lbm_ctx* ctx) {
@@ -118,7 +115,6 @@ void fill_kparams(lbm_ctx* ctx) {
     k.ny = static_cast<int>(ctx->extent[1]);
     k.nz = ctx->D == 3 ? static_cast<int>(ctx->extent[2]) : 1;
     k.N = ctx->N;
-    k.P = plane_stride(ctx);
     const long long rows = static_cast<long long>(k.ny) * k.nz;
     const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads());
     k.chunks = rl.chunks;
@@ -244,9 +240,14 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
         lbm::row_launch(static_cast<int>(extent[0]), rows, lbm::step_max_threads());
     if (rl.blocks >= (1LL << 31) || rl.blocks * rl.bx >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID, "grid too large for one launch");
-    if ((N + lbm::kPlanePad) * (precision == LBM_FP64 ? 8LL : 4LL) >= (1LL << 32))
+    // The kernels address one slab of the slowest axis (all populations of a
+    // z-plane in 3D, of a row in 2D) with 32-bit byte offsets.
+    const long long slab = (D == 3 ? extent[0] * extent[1] : extent[0]) * Q *
+                           (precision == LBM_FP64 ? 8LL : 4LL);
+    if (slab >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID,
-                    "grid too large: one population plane must stay below 4 GiB");
+                    "grid too large: the populations of one slab (z-plane in 3D, row in 2D) "
+                    "must stay below 4 GiB");
     if (!omega_ok(omega)) return fail(nullptr, LBM_E_INVALID, "omega must be in [0, 2)");
     if (precision == LBM_FP32_SHIFTED && (!std::isfinite(rho0) || rho0 < 0.0))
         return fail(nullptr, LBM_E_INVALID, "rho0 must be finite and >= 0");

@@ -9,14 +9,7 @@
 
 #include "lbm_model.h"
 
-#ifndef LBM_PLANE_PAD
-#define LBM_PLANE_PAD 0
-#endif
-
 namespace lbm {
-
-// Padding (elements) added to every population plane of the stored state.
-constexpr long long kPlanePad = LBM_PLANE_PAD;
 
 // Per-context constants, passed to every kernel by value.
 //
@@ -29,7 +22,6 @@ struct KParams {
     int chunks;               // blocks per grid row (x direction)
     int bx;                   // threads per block (multiple of 64)
     long long N;              // cells
-    long long P;              // elements between population planes (N + padding)
     double omega;             // relaxation frequency
     double omc;               // 1 - omega as used by the kernels (float-rounded for F32S)
     double omega_eff;         // 1 - omc, so that omc + omega_eff = 1 exactly

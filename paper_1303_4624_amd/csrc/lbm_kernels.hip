@@ -109,9 +109,28 @@ __device__ __forceinline__ int wrap_idx(int v, int n) {
 
 struct Cell {
     int x, y, z;        // x clamped into the grid for inactive lanes
+    int row;            // y + ny*z
     bool active;
     long long c;        // linear cell index
 };
+
+// Storage layout of the populations: the Q populations of one grid row
+// (fixed y[, z]) are contiguous, population-major inside the row, so
+// element (i, c) with c = row*nx + x sits at (row*Q + i)*nx + x.  A step
+// then writes one contiguous run per row and reads Q runs from the few
+// source rows around it.
+template <int Q>
+struct PopIdx {
+    long long base;     // row*Q*nx + x
+    long long nx;
+    __device__ __forceinline__ long long operator()(int i) const { return base + i * nx; }
+};
+
+template <int Q>
+__device__ __forceinline__ PopIdx<Q> pop_idx(const KParams& k, long long c) {
+    const long long row = c / k.nx;
+    return {row * Q * k.nx + (c - row * k.nx), k.nx};
+}
 
 // Row-blocked mapping: block b covers threads [chunk*bx, chunk*bx + bx) of
 // grid row `row` = y + ny*z.  y and z are uniform over the block.
@@ -132,6 +151,7 @@ __device__ __forceinline__ Cell row_cell(const KParams& k) {
     const int x = chunk * k.bx + static_cast<int>(threadIdx.x);
     cl.active = x < k.nx;
     cl.x = cl.active ? x : 0;
+    cl.row = row;
     cl.y = row % k.ny;
     cl.z = row / k.ny;
     cl.c = (static_cast<long long>(row)) * k.nx + cl.x;
@@ -141,60 +161,69 @@ __device__ __forceinline__ Cell row_cell(const KParams& k) {
 // Gather v_i = src_i(x - SIGN*e_i) with periodic wrap on every axis.
 // SIGN = +1 is the pull of the forward update, SIGN = -1 the transposed
 // (adjoint) streaming.
+//
+// Addresses: a 64-bit base per source slab of the slowest axis (z-planes in
+// 3D, rows in 2D; wave-uniform) plus a 32-bit byte offset inside the slab
+// (row, population run, x).  A slab stays below 4 GiB (checked on the host).
 template <class M, int SIGN, class S>
 __device__ __forceinline__ void gather(const S* __restrict__ src, const KParams& k, const Cell& cl,
                                        S (&v)[M::Q]) {
-    // Byte offsets inside one population plane fit in 32 bits (N * 8 < 2^32
-    // is checked on the host): per lane for x, wave-uniform for the y/z rows.
-    unsigned xb[kW], yb[kW], zb[kW];
+    const unsigned runb = static_cast<unsigned>(k.nx) * static_cast<unsigned>(sizeof(S));
+    const unsigned rowb = runb * static_cast<unsigned>(M::Q);
+    const char* base = reinterpret_cast<const char*>(src);
+    unsigned xb[kW], yb[kW];
+    const char* sb[kW];
     static_for<kW>([&](auto DI) {
         constexpr int d = decltype(DI)::value - kMaxDisp;
         xb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.x - d, k.nx)) * sizeof(S);
-        yb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.y - d, k.ny) * k.nx) * sizeof(S);
-        zb[d + kMaxDisp] = (M::D == 3)
-            ? static_cast<unsigned>(wrap_idx(cl.z - d, k.nz)) * static_cast<unsigned>(k.nx * k.ny) *
-                  static_cast<unsigned>(sizeof(S))
-            : 0u;
+        if constexpr (M::D == 3) {
+            yb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.y - d, k.ny)) * rowb;
+            sb[d + kMaxDisp] = base + static_cast<unsigned long long>(wrap_idx(cl.z - d, k.nz)) *
+                                          (static_cast<unsigned long long>(rowb) * k.ny);
+        } else {
+            yb[d + kMaxDisp] = 0u;
+            sb[d + kMaxDisp] =
+                base + static_cast<unsigned long long>(wrap_idx(cl.y - d, k.ny)) * rowb;
+        }
     });
-    // One live 64-bit plane pointer, advanced by the plane size.
-    const char* plane = reinterpret_cast<const char*>(src);
-    const unsigned long long pbytes = static_cast<unsigned long long>(k.P) * sizeof(S);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = SIGN * M::table.e[i][0];
         constexpr int ey = SIGN * M::table.e[i][1];
         constexpr int ez = SIGN * M::table.e[i][2];
-        const unsigned off = zb[ez + kMaxDisp] + yb[ey + kMaxDisp] + xb[ex + kMaxDisp];
+        constexpr int ds = (M::D == 3) ? ez : ey;      // displacement along the slab axis
+        constexpr int dy = (M::D == 3) ? ey : 0;
+        const unsigned off = yb[dy + kMaxDisp] + static_cast<unsigned>(i) * runb + xb[ex + kMaxDisp];
 #if LBM_NT_LOAD
-        v[i] = __builtin_nontemporal_load(reinterpret_cast<const S*>(plane + off));
+        v[i] = __builtin_nontemporal_load(reinterpret_cast<const S*>(sb[ds + kMaxDisp] + off));
 #else
-        v[i] = *reinterpret_cast<const S*>(plane + off);
+        v[i] = *reinterpret_cast<const S*>(sb[ds + kMaxDisp] + off);
 #endif
-        plane += pbytes;
     });
 }
 
-// Writes population planes in increasing order through one running 64-bit
-// plane pointer and a 32-bit byte offset of the cell inside the plane.
-// Lanes past the end of a ragged row have x clamped to 0: they compute
-// bit-identical values for cell (0, y, z) and store them there too, which
-// keeps the stores free of per-store branches.
+// Writes the populations of a cell in increasing order through one running
+// 64-bit pointer (row start + population run) and the cell's 32-bit byte
+// offset inside the run.  Lanes past the end of a ragged row have x clamped
+// to 0: they compute bit-identical values for cell (0, y, z) and store them
+// there too, which keeps the stores free of per-store branches.
 template <class S>
 struct PlaneWriter {
-    char* plane;
-    unsigned long long pbytes;
+    char* run;
+    unsigned long long runb;
     unsigned off;
-    __device__ __forceinline__ PlaneWriter(S* dst, const KParams& k, const Cell& cl)
-        : plane(reinterpret_cast<char*>(dst)),
-          pbytes(static_cast<unsigned long long>(k.P) * sizeof(S)),
-          off(static_cast<unsigned>(cl.c) * static_cast<unsigned>(sizeof(S))) {}
+    __device__ __forceinline__ PlaneWriter(S* dst, const KParams& k, const Cell& cl, int Q)
+        : run(reinterpret_cast<char*>(dst) +
+              static_cast<unsigned long long>(cl.row) * Q * k.nx * sizeof(S)),
+          runb(static_cast<unsigned long long>(k.nx) * sizeof(S)),
+          off(static_cast<unsigned>(cl.x) * static_cast<unsigned>(sizeof(S))) {}
     __device__ __forceinline__ void put(S val) {
 #if LBM_NT_STORE
-        __builtin_nontemporal_store(val, reinterpret_cast<S*>(plane + off));
+        __builtin_nontemporal_store(val, reinterpret_cast<S*>(run + off));
 #else
-        *reinterpret_cast<S*>(plane + off) = val;
+        *reinterpret_cast<S*>(run + off) = val;
 #endif
-        plane += pbytes;
+        run += runb;
     }
 };
 
@@ -332,7 +361,7 @@ void k_step(const typename P::S* __restrict__ src,
     const double wr = k.omega_eff * mc.rho;
     const double wd = k.omega_eff * mc.dr;
     const R omc = R(k.omc);
-    PlaneWriter<S> out_w(dst, k, cl);
+    PlaneWriter<S> out_w(dst, k, cl, Q);
 
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
@@ -375,6 +404,7 @@ __device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const K
     const double d = T * k.invT0 - 1.0;
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
+    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
     static_for<M::G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
         const GCoef gc = group_coef(k, g, u2, d);
@@ -384,10 +414,9 @@ __device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const K
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double h = horner_h(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
             if constexpr (P::shifted) {
-                f[static_cast<long long>(i) * k.P + c] =
-                    static_cast<float>(w * (r - k.rho0) + w * r * h);
+                f[pi(i)] = static_cast<float>(w * (r - k.rho0) + w * r * h);
             } else {
-                f[static_cast<long long>(i) * k.P + c] = w * r * (1.0 + h);
+                f[pi(i)] = w * r * (1.0 + h);
             }
         });
     });
@@ -427,14 +456,15 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(const double* __restrict__ f
                                                     typename P::S* __restrict__ f, KParams k) {
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= k.N) return;
+    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int g = M::table.group[i];
         const double val = fin[static_cast<long long>(i) * k.N + c];
         if constexpr (P::shifted)
-            f[static_cast<long long>(i) * k.P + c] = static_cast<float>(val - k.W[g] * k.rho0);
+            f[pi(i)] = static_cast<float>(val - k.W[g] * k.rho0);
         else
-            f[static_cast<long long>(i) * k.P + c] = val;
+            f[pi(i)] = val;
     });
 }
 
@@ -443,10 +473,11 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(const typename P::S* __restr
                                                     double* __restrict__ fout, KParams k) {
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= k.N) return;
+    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int g = M::table.group[i];
-        const double val = static_cast<double>(f[static_cast<long long>(i) * k.P + c]);
+        const double val = static_cast<double>(f[pi(i)]);
         fout[static_cast<long long>(i) * k.N + c] = P::shifted ? val + k.W[g] * k.rho0 : val;
     });
 }
@@ -458,11 +489,12 @@ __device__ __forceinline__ void cell_sums(const S* __restrict__ f, const KParams
     m0 = 0.0;
     j[0] = j[1] = j[2] = 0.0;
     en = 0.0;
+    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
         constexpr int ee = M::table.e2[M::table.group[i]];
-        const double val = static_cast<double>(f[static_cast<long long>(i) * k.P + c]);
+        const double val = static_cast<double>(f[pi(i)]);
         m0 += val;
         if constexpr (ex != 0) j[0] += double(ex) * val;
         if constexpr (ey != 0) j[1] += double(ey) * val;
@@ -558,10 +590,11 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     if (c < k.N) {
         const double g = dLdrho[c];
         double m0 = 0.0;
+        const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
         static_for<M::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            m0 += static_cast<double>(fn[static_cast<long long>(i) * k.P + c]);
-            lam[static_cast<long long>(i) * k.P + c] = static_cast<S>(g);
+            m0 += static_cast<double>(fn[pi(i)]);
+            lam[pi(i)] = static_cast<S>(g);
         });
         const double r = P::shifted ? k.rho0 + m0 : m0;
         acc[0] = g * r;
@@ -614,7 +647,7 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
 
     if constexpr (!COLLIDE) {
         // transposed streaming only
-        PlaneWriter<S> wt(ldst, k, cl);
+        PlaneWriter<S> wt(ldst, k, cl, Q);
         static_for<Q>([&](auto I) { wt.put(mu[decltype(I)::value]); });
         return;
     }
@@ -691,7 +724,7 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
     const R ge = R(w * at * invr * (1.0 / D));
     const R gr = R(w * grho);
     const R omc = R(k.omc);
-    PlaneWriter<S> out_w(ldst, k, cl);
+    PlaneWriter<S> out_w(ldst, k, cl, Q);
 
     static_for<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -726,6 +759,7 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
     const double d = T[c] * k.invT0 - 1.0;
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
+    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
     double sd = 0.0;
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
@@ -736,7 +770,7 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double s = edot<ex, ey, ez>(utx, uty, utz);
             const double pd = gd.c0 + s * (gd.c1 + s * gd.c2);
-            tg += static_cast<double>(lam[static_cast<long long>(i) * k.P + c]) * pd;
+            tg += static_cast<double>(lam[pi(i)]) * pd;
         });
         sd += k.W[g] * tg;
     });

@@ -84,6 +84,9 @@ def test_create_accepts_valid_arguments(name):
     assert _create_status(**_args(name, precision=L.LBM_FP32_SHIFTED)) == L.LBM_OK
     assert _create_status(**_args(name, omega=0.0)) == L.LBM_OK
     assert _create_status(**_args(name, extent=[1] * MODELS[name][0])) == L.LBM_OK
+    # largest slabs below the 4 GiB limit of one z-plane (3D) or row (2D)
+    big = [1024, 1024, 3] if name == "D3Q95" else [1 << 24, 3]
+    assert _create_status(**_args(name, extent=big, precision=L.LBM_FP32_SHIFTED)) == L.LBM_OK
 
 
 def test_create_rejections():
@@ -104,6 +107,8 @@ def test_create_rejections():
         (dict(c=a["c"] * 1.001), L.LBM_E_INVALID),       # weight equations fail
         (dict(c=-1.0), L.LBM_E_INVALID),
         (dict(extent=[8, 0, 8]), L.LBM_E_INVALID),
+        # one z-plane of FP64 populations: 4096^2 * 95 * 8 B > 4 GiB
+        (dict(extent=[4096, 4096, 1]), L.LBM_E_INVALID),
         (dict(extent=[8, -3, 8]), L.LBM_E_INVALID),
         (dict(omega=2.0), L.LBM_E_INVALID),
         (dict(omega=-0.1), L.LBM_E_INVALID),
