@@ -116,7 +116,7 @@ void fill_kparams(lbm_ctx* ctx) {
     k.nz = ctx->D == 3 ? static_cast<int>(ctx->extent[2]) : 1;
     k.N = ctx->N;
     const long long rows = static_cast<long long>(k.ny) * k.nz;
-    const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads());
+    const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads(ctx->prec));
     k.chunks = rl.chunks;
     k.bx = rl.bx;
     k.omega = ctx->omega;
@@ -237,7 +237,8 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
     }
     const long long rows = N / extent[0];
     const lbm::RowLaunch rl =
-        lbm::row_launch(static_cast<int>(extent[0]), rows, lbm::step_max_threads());
+        lbm::row_launch(static_cast<int>(extent[0]), rows,
+                        lbm::step_max_threads(precision == LBM_FP64 ? Prec::F64 : Prec::F32S));
     if (rl.blocks >= (1LL << 31) || rl.blocks * rl.bx >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID, "grid too large for one launch");
     // The kernels address one slab of the slowest axis (all populations of a

@@ -48,8 +48,8 @@ struct RowLaunch {
 };
 
 RowLaunch row_launch(int nx, long long rows, int max_threads);
-// Largest block size the row-blocked kernels are compiled for.
-int step_max_threads();
+// Largest block size the row-blocked kernels of a precision are compiled for.
+int step_max_threads(Prec p);
 
 // Number of blocks of the grid-stride reduction kernels.
 int reduce_blocks(long long N);

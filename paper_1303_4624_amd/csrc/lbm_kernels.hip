@@ -40,6 +40,9 @@ namespace {
 #ifndef LBM_STEP_MAXB
 #define LBM_STEP_MAXB 512
 #endif
+#ifndef LBM_F64_MAXB
+#define LBM_F64_MAXB 256
+#endif
 #ifndef LBM_NT_STORE
 #define LBM_NT_STORE 1
 #endif
@@ -62,7 +65,6 @@ namespace {
 #define LBM_F32S_SUM64 1
 #endif
 constexpr int kBlock = 256;            // threads per block of the cell-parallel kernels
-constexpr int kStepMaxB = LBM_STEP_MAXB;  // largest block of the row-blocked kernels
 constexpr int kW = 2 * kMaxDisp + 1;   // distinct displacement components
 
 template <class F, int... I>
@@ -74,15 +76,19 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(static_cast<F&&>(f), std::make_integer_sequence<int, N>{});
 }
 
+// Largest block of the row-blocked kernels (step, adjoint) per precision:
+// float64 keeps 256 threads so that a wave may use up to 512 VGPRs.
 struct F64T {
     using S = double;
     using Acc = double;   // type of the per-cell moment sums
+    static constexpr int max_block = LBM_F64_MAXB;
     static constexpr bool shifted = false;
     static constexpr int waves = 1;
     static constexpr int adj_waves = 1;
 };
 struct F32ST {
     using S = float;
+    static constexpr int max_block = LBM_STEP_MAXB;
     // Moment sums of the float32 deviations in float64: a float32 sum of 95
     // terms is off by a few ulps of sum |e|^2 |g|, the same in every node of
     // a uniform region, so without it such regions drift coherently.
@@ -328,7 +334,7 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accu
 // with omc + omega_eff = 1 exactly, so mass, momentum and energy are
 // conserved up to the rounding of each cell's own values.
 template <class M, class P, bool STORE_MOM>
-__global__ __launch_bounds__(kStepMaxB) __attribute__((amdgpu_waves_per_eu(P::waves)))
+__global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
 void k_step(const typename P::S* __restrict__ src,
                                                  typename P::S* __restrict__ dst, KParams k,
                                                  typename P::S* __restrict__ mom) {
@@ -630,7 +636,7 @@ __device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, do
 // Output lambda^t_i = omc mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2).
 // partA[block] += sum over the block's cells of A = rho S0.
 template <class M, class P, bool COLLIDE>
-__global__ __launch_bounds__(kStepMaxB) __attribute__((amdgpu_waves_per_eu(P::adj_waves)))
+__global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::adj_waves)))
 void k_adjoint(const typename P::S* __restrict__ lsrc,
                                                     typename P::S* __restrict__ ldst,
                                                     const typename P::S* __restrict__ mom,
@@ -793,11 +799,11 @@ inline unsigned cell_blocks(long long N) {
 
 }  // namespace
 
-int step_max_threads() { return kStepMaxB; }
+int step_max_threads(Prec p) { return p == Prec::F64 ? F64T::max_block : F32ST::max_block; }
 
 RowLaunch row_launch(int nx, long long rows, int max_threads) {
     RowLaunch r;
-    const int maxb = max_threads < kStepMaxB ? max_threads : kStepMaxB;
+    const int maxb = max_threads;
     r.chunks = (nx + maxb - 1) / maxb;
     const int per = (nx + r.chunks - 1) / r.chunks;
     r.bx = ((per + 63) / 64) * 64;
