@@ -73,6 +73,11 @@ typedef enum lbm_status {
     LBM_E_NONFINITE = -5     /* a reduced diagnostic is NaN or infinite */
 } lbm_status;
 
+typedef enum lbm_streaming {
+    LBM_STREAM_AB = 0,       /* two population buffers, pull from one into the other (default) */
+    LBM_STREAM_AA = 1        /* one buffer updated in place (AA pattern), half the memory */
+} lbm_streaming;
+
 typedef enum lbm_precision {
     LBM_FP64 = 0,            /* populations and arithmetic in float64 */
     LBM_FP32_SHIFTED = 1     /* float32 deviations g_i = f_i - w_i rho0, float32 arithmetic */
@@ -139,10 +144,32 @@ int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const double* w,
 int lbm_workspace_bytes(const lbm_ctx* ctx, size_t* pop_bytes, size_t* scratch_bytes);
 
 /*
- * lbm_bind - attach caller-owned device memory: two population buffers
- * (pull streaming reads one and writes the other) and a scratch buffer of the
- * sizes lbm_workspace_bytes reports.  Records the current HIP device.
- * Re-binding is allowed and drops the initialised state.
+ * lbm_set_streaming - choose how a step moves the populations; call before
+ * lbm_bind (LBM_E_STATE after it).
+ *   LBM_STREAM_AB (default): two buffers; a step gathers f*_i(x - e_i) from
+ *     one and writes f*(t + 1) to the other.
+ *   LBM_STREAM_AA: one buffer updated in place, so a grid twice as large fits
+ *     in the same memory.  Steps alternate between a kernel that reads the
+ *     arriving values from the neighbours' opposite slots and writes each
+ *     result into the neighbour it streams to, and a kernel that reads and
+ *     writes its own cell only (populations stored in the opposite slot).
+ *     Every location is read and written by one thread only.  The update
+ *     (the update rule that opens the method) and its arithmetic are those
+ *     of LBM_STREAM_AB (bit-identical results);
+ *     lbm_moments, lbm_conservation and lbm_get/set_populations follow the
+ *     alternating storage.  Fixed planes, checkpointed runs and the adjoint
+ *     need LBM_STREAM_AB and return LBM_E_UNSUPPORTED.
+ * Returns LBM_E_INVALID for another scheme, LBM_E_UNSUPPORTED for
+ * LBM_STREAM_AA while planes are held.
+ */
+int lbm_set_streaming(lbm_ctx* ctx, int scheme);
+
+/*
+ * lbm_bind - attach caller-owned device memory: population buffers f_a and
+ * f_b (LBM_STREAM_AB: both, distinct; LBM_STREAM_AA: f_a only, f_b must be
+ * NULL) and a scratch buffer, of the sizes lbm_workspace_bytes reports, all
+ * 256-byte aligned.  Records the current HIP device.  Re-binding is allowed
+ * and drops the initialised state.
  */
 int lbm_bind(lbm_ctx* ctx, void* f_a, void* f_b, void* scratch);
 
@@ -208,7 +235,8 @@ int lbm_conservation(lbm_ctx* ctx, double* out);
  * The held planes are not touched until the next step (set the initial
  * state with lbm_init_fields).  n_lo = n_hi = 0 restores a fully periodic
  * lattice.  Returns LBM_E_INVALID for n_lo, n_hi < 0, n_lo + n_hi >
- * extent[D-1], NULL or non-positive states, LBM_E_NONFINITE for NaN/Inf.
+ * extent[D-1], NULL or non-positive states, LBM_E_NONFINITE for NaN/Inf,
+ * LBM_E_UNSUPPORTED with LBM_STREAM_AA.
  * lbm_run_checkpointed and lbm_adjoint return LBM_E_UNSUPPORTED while
  * planes are held.
  */

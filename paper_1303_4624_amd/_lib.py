@@ -25,12 +25,14 @@ LBM_E_STATE = -4
 LBM_E_NONFINITE = -5
 LBM_FP64 = 0
 LBM_FP32_SHIFTED = 1
+LBM_STREAM_AB = 0
+LBM_STREAM_AA = 1
 LBM_MAX_Q = 95
 
 EXPORTED = [
     "lbm_velocity_set", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments",
-    "lbm_conservation", "lbm_set_fixed_planes", "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
+    "lbm_conservation", "lbm_set_fixed_planes", "lbm_set_streaming", "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_str",
     "lbm_last_error",
 ]
@@ -64,6 +66,7 @@ _SIGS = {
     "lbm_moments": (_c.c_int, [_vp, _vp, _vp, _vp]),
     "lbm_conservation": (_c.c_int, [_vp, _pd]),
     "lbm_set_fixed_planes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _pd, _pd]),
+    "lbm_set_streaming": (_c.c_int, [_vp, _c.c_int]),
     "lbm_set_omega": (_c.c_int, [_vp, _c.c_double]),
     "lbm_checkpoint_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _psz]),
     "lbm_run_checkpointed": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _vp, _sz]),
@@ -191,6 +194,10 @@ def lbm_set_fixed_planes(ctx, n_lo: int, n_hi: int, state_lo=None, state_hi=None
     _check(library().lbm_set_fixed_planes(
         ctx, int(n_lo), int(n_hi), None if lo is None else lo.ctypes.data_as(_pd),
         None if hi is None else hi.ctypes.data_as(_pd)), "lbm_set_fixed_planes", ctx)
+
+
+def lbm_set_streaming(ctx, scheme: int) -> None:
+    _check(library().lbm_set_streaming(ctx, int(scheme)), "lbm_set_streaming", ctx)
 
 
 def lbm_set_omega(ctx, omega: float) -> None:

@@ -39,6 +39,7 @@ struct lbm_ctx {
     bool bound = false;
     bool initialized = false;
     KParams kp{};
+    bool aa = false;                // one buffer, in-place AA-pattern steps
     int hold_lo = 0, hold_hi = 0;   // planes held at f^eq at each end of the slowest axis
     lbm::FixedState hold[2]{};
     std::string err;
@@ -109,8 +110,12 @@ int check_dev(lbm_ctx* ctx, const void* p, size_t bytes, const char* name) {
     return LBM_OK;
 }
 
+// Storage form the state starts in after lbm_init_fields / lbm_set_populations.
+int initial_form(const lbm_ctx* ctx) { return ctx->aa ? lbm::kFormSwapped : lbm::kFormAB; }
+
 void fill_kparams(lbm_ctx* ctx) {
     KParams& k = ctx->kp;
+    if (!ctx->initialized) k.form = initial_form(ctx);
     k.nx = static_cast<int>(ctx->extent[0]);
     k.ny = static_cast<int>(ctx->extent[1]);
     k.nz = ctx->D == 3 ? static_cast<int>(ctx->extent[2]) : 1;
@@ -291,25 +296,28 @@ LBM_API int lbm_bind(lbm_ctx* ctx, void* f_a, void* f_b, void* scratch) {
         if (p && reinterpret_cast<uintptr_t>(p) % kAlign != 0)
             return fail(ctx, LBM_E_INVALID, "buffers must be 256-byte aligned");
     }
+    if (ctx->aa && f_b)
+        return fail(ctx, LBM_E_INVALID, "in-place (AA) streaming uses one buffer: f_b must be NULL");
     const int saved = ctx->device;
     ctx->device = dev;
     int rc;
     if ((rc = check_dev(ctx, f_a, pop_bytes(ctx), "f_a")) != LBM_OK ||
-        (rc = check_dev(ctx, f_b, pop_bytes(ctx), "f_b")) != LBM_OK ||
+        (!ctx->aa && (rc = check_dev(ctx, f_b, pop_bytes(ctx), "f_b")) != LBM_OK) ||
         (rc = check_dev(ctx, scratch, scratch_bytes(ctx), "scratch")) != LBM_OK) {
         ctx->device = saved;
         return rc;
     }
-    if (f_a == f_b) {
+    if (!ctx->aa && f_a == f_b) {
         ctx->device = saved;
         return fail(ctx, LBM_E_INVALID, "f_a and f_b must be distinct buffers");
     }
     ctx->f[0] = f_a;
-    ctx->f[1] = f_b;
+    ctx->f[1] = ctx->aa ? nullptr : f_b;
     ctx->cur = 0;
     ctx->scratch = scratch;
     ctx->bound = true;
     ctx->initialized = false;
+    ctx->kp.form = initial_form(ctx);
     ctx->err.clear();
     return LBM_OK;
 }
@@ -323,9 +331,12 @@ LBM_API int lbm_init_fields(lbm_ctx* ctx, const double* rho, const double* U, co
     if ((rc = check_dev(ctx, U, nb * ctx->D, "U")) != LBM_OK) return rc;
     if ((rc = check_dev(ctx, T, nb, "T")) != LBM_OK) return rc;
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
-    hipError_t e = lbm::launch_init(ctx->model, ctx->prec, ctx->kp, rho, U, T, ctx->f[ctx->cur],
+    KParams kp = ctx->kp;
+    kp.form = initial_form(ctx);
+    hipError_t e = lbm::launch_init(ctx->model, ctx->prec, kp, rho, U, T, ctx->f[ctx->cur],
                                     ctx->stream);
     if (e != hipSuccess) return fail_hip(ctx, e, "init kernel");
+    ctx->kp.form = kp.form;
     ctx->initialized = true;
     return LBM_OK;
 }
@@ -337,9 +348,11 @@ LBM_API int lbm_set_populations(lbm_ctx* ctx, const double* f) {
     if ((rc = check_dev(ctx, f, static_cast<size_t>(ctx->N) * ctx->Q * 8, "f")) != LBM_OK)
         return rc;
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
-    hipError_t e =
-        lbm::launch_set_pop(ctx->model, ctx->prec, ctx->kp, f, ctx->f[ctx->cur], ctx->stream);
+    KParams kp = ctx->kp;
+    kp.form = initial_form(ctx);
+    hipError_t e = lbm::launch_set_pop(ctx->model, ctx->prec, kp, f, ctx->f[ctx->cur], ctx->stream);
     if (e != hipSuccess) return fail_hip(ctx, e, "set-populations kernel");
+    ctx->kp.form = kp.form;
     ctx->initialized = true;
     return LBM_OK;
 }
@@ -361,6 +374,16 @@ LBM_API int lbm_step(lbm_ctx* ctx, int n) {
     if ((rc = require_init(ctx)) != LBM_OK) return rc;
     if (n < 0) return fail(ctx, LBM_E_INVALID, "n must be >= 0");
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    if (ctx->aa) {
+        for (int t = 0; t < n; ++t) {
+            const bool push = ctx->kp.form == lbm::kFormSwapped;
+            hipError_t e =
+                lbm::launch_step_aa(ctx->model, ctx->prec, ctx->kp, ctx->f[0], push, ctx->stream);
+            if (e != hipSuccess) return fail_hip(ctx, e, "in-place step kernel");
+            ctx->kp.form = push ? lbm::kFormPushed : lbm::kFormSwapped;
+        }
+        return LBM_OK;
+    }
     for (int t = 0; t < n; ++t) {
         hipError_t e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
                                         ctx->f[1 - ctx->cur], nullptr, ctx->stream);
@@ -383,6 +406,8 @@ LBM_API int lbm_set_fixed_planes(lbm_ctx* ctx, int n_lo, int n_hi, const double*
     const int64_t L = ctx->extent[ctx->D - 1];
     if (n_lo < 0 || n_hi < 0 || static_cast<int64_t>(n_lo) + n_hi > L)
         return fail(ctx, LBM_E_INVALID, "need n_lo, n_hi >= 0 and n_lo + n_hi <= extent[D-1]");
+    if (ctx->aa && n_lo + n_hi > 0)
+        return fail(ctx, LBM_E_UNSUPPORTED, "fixed planes need two-buffer streaming");
     const double* st[2] = {state_lo, state_hi};
     const int cnt[2] = {n_lo, n_hi};
     lbm::FixedState fs[2]{};
@@ -464,6 +489,18 @@ LBM_API int lbm_conservation(lbm_ctx* ctx, double* out) {
     return LBM_OK;
 }
 
+LBM_API int lbm_set_streaming(lbm_ctx* ctx, int scheme) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (scheme != LBM_STREAM_AB && scheme != LBM_STREAM_AA)
+        return fail(ctx, LBM_E_INVALID, "scheme must be LBM_STREAM_AB or LBM_STREAM_AA");
+    if (ctx->bound) return fail(ctx, LBM_E_STATE, "choose the streaming scheme before lbm_bind");
+    if (scheme == LBM_STREAM_AA && ctx->hold_lo + ctx->hold_hi > 0)
+        return fail(ctx, LBM_E_UNSUPPORTED, "fixed planes need two-buffer streaming");
+    ctx->aa = scheme == LBM_STREAM_AA;
+    ctx->kp.form = initial_form(ctx);
+    return LBM_OK;
+}
+
 LBM_API int lbm_set_omega(lbm_ctx* ctx, double omega) {
     if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
     if (!omega_ok(omega)) return fail(ctx, LBM_E_INVALID, "omega must be in [0, 2)");
@@ -516,6 +553,8 @@ LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckp
     if (ctx->hold_lo + ctx->hold_hi > 0)
         return fail(ctx, LBM_E_UNSUPPORTED, "checkpointed runs need an all-periodic lattice "
                                             "(fixed planes are set)");
+    if (ctx->aa)
+        return fail(ctx, LBM_E_UNSUPPORTED, "checkpointed runs need two-buffer streaming");
     const CkLayout c = ck_layout(ctx, n, k, keep);
     if (ckpt_bytes < c.total) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
     if ((rc = check_dev(ctx, ckpt, c.total, "ckpt")) != LBM_OK) return rc;
@@ -594,6 +633,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
     if (ctx->hold_lo + ctx->hold_hi > 0)
         return fail(ctx, LBM_E_UNSUPPORTED, "the adjoint needs an all-periodic lattice "
                                             "(fixed planes are set)");
+    if (ctx->aa) return fail(ctx, LBM_E_UNSUPPORTED, "the adjoint needs two-buffer streaming");
     if (dL_domega && std::fabs(1.0 - ctx->omega) < 1e-3)
         return fail(ctx, LBM_E_INVALID,
                     "the omega gradient needs |1 - omega| >= 1e-3 (it is divided by 1 - omega)");

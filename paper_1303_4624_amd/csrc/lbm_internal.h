@@ -17,8 +17,14 @@ namespace lbm {
 // the X-only parts of its coefficients are precomputed here:
 //   K1 = (X - D)/2, K2 = (D + 2 - X)/4, K3 = (X^2 - 2(D + 2)X + D(D + 2))/8,
 //   K4 = (X - D - 2)/2, K5 = (X - D - 4)/4.
+// Storage forms of the population buffer (see the kernels' PopAt).
+constexpr int kFormAB = 0;        // two buffers: run i of cell c
+constexpr int kFormSwapped = 1;   // in place, after an even number of steps: run opp(i) of c
+constexpr int kFormPushed = 2;    // in place, after an odd number of steps: run i of c + e_i
+
 struct KParams {
     int nx, ny, nz;           // nz = 1 in 2D
+    int form;                 // storage form of the state the kernel reads or writes
     int chunks;               // blocks per grid row (x direction)
     int bx;                   // threads per block (multiple of 64)
     long long N;              // cells
@@ -67,6 +73,10 @@ hipError_t launch_get_pop(ModelId m, Prec p, const KParams& kp, const void* f, d
                           hipStream_t s);
 hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, void* dst,
                        void* mom_out, hipStream_t s);
+// In-place step (AA pattern): push = true reads the swapped form and writes
+// the pushed form, push = false the reverse.
+hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool push,
+                          hipStream_t s);
 hipError_t launch_moments(ModelId m, Prec p, const KParams& kp, const void* f, double* rho,
                           double* U, double* T, hipStream_t s);
 hipError_t launch_conservation(ModelId m, Prec p, const KParams& kp, const void* f,

@@ -30,6 +30,7 @@
 // of the Maxwellian, collected in powers of s.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
 #include <utility>
 
 #include "lbm_internal.h"
@@ -125,18 +126,36 @@ struct Cell {
 // element (i, c) with c = row*nx + x sits at (row*Q + i)*nx + x.  A step
 // then writes one contiguous run per row and reads Q runs from the few
 // source rows around it.
-template <int Q>
-struct PopIdx {
-    long long base;     // row*Q*nx + x
-    long long nx;
-    __device__ __forceinline__ long long operator()(int i) const { return base + i * nx; }
+//
+// Where population i of cell c is stored depends on the form of the state
+// (KParams::form): kFormAB, run i of cell c; kFormSwapped (in-place AA
+// pattern after an even number of steps), run opp(i) of cell c;
+// kFormPushed (AA after an odd number), run i of cell c + e_i.
+template <class M>
+struct PopAt {
+    long long row;
+    int x, y, z;
+    __device__ __forceinline__ PopAt(const KParams& k, long long c) {
+        row = c / k.nx;
+        x = static_cast<int>(c - row * k.nx);
+        y = static_cast<int>(row % k.ny);
+        z = static_cast<int>(row / k.ny);
+    }
+    template <int i>
+    __device__ __forceinline__ long long at(const KParams& k) const {
+        constexpr int Q = M::Q;
+        if (k.form == kFormPushed) {
+            constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+            const long long xr = wrap_idx(x + ex, k.nx);
+            const long long yr = wrap_idx(y + ey, k.ny);
+            const long long r = (M::D == 3) ? static_cast<long long>(wrap_idx(z + ez, k.nz)) * k.ny + yr
+                                            : yr;
+            return (r * Q + i) * k.nx + xr;
+        }
+        const int slot = (k.form == kFormSwapped) ? M::table.opp[i] : i;
+        return (row * Q + slot) * k.nx + x;
+    }
 };
-
-template <int Q>
-__device__ __forceinline__ PopIdx<Q> pop_idx(const KParams& k, long long c) {
-    const long long row = c / k.nx;
-    return {row * Q * k.nx + (c - row * k.nx), k.nx};
-}
 
 // Row-blocked mapping: block b covers threads [chunk*bx, chunk*bx + bx) of
 // grid row `row` = y + ny*z.  y and z are uniform over the block.
@@ -164,47 +183,73 @@ __device__ __forceinline__ Cell row_cell(const KParams& k) {
     return cl;
 }
 
+// Addresses around one cell: a 64-bit base per slab of the slowest axis
+// (z-planes in 3D, rows in 2D; wave-uniform) plus a 32-bit byte offset inside
+// the slab (row, population run, x).  A slab stays below 4 GiB (checked on
+// the host).  at<slot, dx, dy, dz>() is the address of population run `slot`
+// of cell (x + dx, y + dy, z + dz), periodic; |d| <= kMaxDisp.
+template <class M, class S, class B>
+struct SlabAddr {
+    unsigned runb;
+    unsigned xb[kW], yb[kW];
+    B* sb[kW];
+    __device__ __forceinline__ SlabAddr(B* base, const KParams& k, const Cell& cl) {
+        runb = static_cast<unsigned>(k.nx) * static_cast<unsigned>(sizeof(S));
+        const unsigned rowb = runb * static_cast<unsigned>(M::Q);
+        static_for<kW>([&](auto DI) {
+            constexpr int d = decltype(DI)::value - kMaxDisp;   // table entry d: cell at -d
+            xb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.x - d, k.nx)) * sizeof(S);
+            if constexpr (M::D == 3) {
+                yb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.y - d, k.ny)) * rowb;
+                sb[d + kMaxDisp] = base + static_cast<unsigned long long>(wrap_idx(cl.z - d, k.nz)) *
+                                              (static_cast<unsigned long long>(rowb) * k.ny);
+            } else {
+                yb[d + kMaxDisp] = 0u;
+                sb[d + kMaxDisp] =
+                    base + static_cast<unsigned long long>(wrap_idx(cl.y - d, k.ny)) * rowb;
+            }
+        });
+    }
+    template <int slot, int dx, int dy, int dz>
+    __device__ __forceinline__ B* at() const {
+        constexpr int ds = (M::D == 3) ? dz : dy;      // along the slab axis
+        constexpr int dr = (M::D == 3) ? dy : 0;       // rows inside a slab
+        const unsigned off = yb[kMaxDisp - dr] + static_cast<unsigned>(slot) * runb + xb[kMaxDisp - dx];
+        return sb[kMaxDisp - ds] + off;
+    }
+};
+
+template <class S>
+__device__ __forceinline__ S load_pop(const char* p) {
+#if LBM_NT_LOAD
+    return __builtin_nontemporal_load(reinterpret_cast<const S*>(p));
+#else
+    return *reinterpret_cast<const S*>(p);
+#endif
+}
+
+template <class S>
+__device__ __forceinline__ void store_pop(char* p, S val) {
+#if LBM_NT_STORE
+    __builtin_nontemporal_store(val, reinterpret_cast<S*>(p));
+#else
+    *reinterpret_cast<S*>(p) = val;
+#endif
+}
+
 // Gather v_i = src_i(x - SIGN*e_i) with periodic wrap on every axis.
 // SIGN = +1 is the pull of the forward update, SIGN = -1 the transposed
 // (adjoint) streaming.
-//
-// Addresses: a 64-bit base per source slab of the slowest axis (z-planes in
-// 3D, rows in 2D; wave-uniform) plus a 32-bit byte offset inside the slab
-// (row, population run, x).  A slab stays below 4 GiB (checked on the host).
 template <class M, int SIGN, class S>
 __device__ __forceinline__ void gather(const S* __restrict__ src, const KParams& k, const Cell& cl,
                                        S (&v)[M::Q]) {
-    const unsigned runb = static_cast<unsigned>(k.nx) * static_cast<unsigned>(sizeof(S));
-    const unsigned rowb = runb * static_cast<unsigned>(M::Q);
-    const char* base = reinterpret_cast<const char*>(src);
-    unsigned xb[kW], yb[kW];
-    const char* sb[kW];
-    static_for<kW>([&](auto DI) {
-        constexpr int d = decltype(DI)::value - kMaxDisp;
-        xb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.x - d, k.nx)) * sizeof(S);
-        if constexpr (M::D == 3) {
-            yb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.y - d, k.ny)) * rowb;
-            sb[d + kMaxDisp] = base + static_cast<unsigned long long>(wrap_idx(cl.z - d, k.nz)) *
-                                          (static_cast<unsigned long long>(rowb) * k.ny);
-        } else {
-            yb[d + kMaxDisp] = 0u;
-            sb[d + kMaxDisp] =
-                base + static_cast<unsigned long long>(wrap_idx(cl.y - d, k.ny)) * rowb;
-        }
-    });
+    const SlabAddr<M, S, const char> ad(reinterpret_cast<const char*>(src), k, cl);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = SIGN * M::table.e[i][0];
         constexpr int ey = SIGN * M::table.e[i][1];
         constexpr int ez = SIGN * M::table.e[i][2];
-        constexpr int ds = (M::D == 3) ? ez : ey;      // displacement along the slab axis
-        constexpr int dy = (M::D == 3) ? ey : 0;
-        const unsigned off = yb[dy + kMaxDisp] + static_cast<unsigned>(i) * runb + xb[ex + kMaxDisp];
-#if LBM_NT_LOAD
-        v[i] = __builtin_nontemporal_load(reinterpret_cast<const S*>(sb[ds + kMaxDisp] + off));
-#else
-        v[i] = *reinterpret_cast<const S*>(sb[ds + kMaxDisp] + off);
-#endif
+        v[i] = load_pop<S>(ad.template at<i, -ex, -ey, -ez>());
     });
 }
 
@@ -224,11 +269,7 @@ struct PlaneWriter {
           runb(static_cast<unsigned long long>(k.nx) * sizeof(S)),
           off(static_cast<unsigned>(cl.x) * static_cast<unsigned>(sizeof(S))) {}
     __device__ __forceinline__ void put(S val) {
-#if LBM_NT_STORE
-        __builtin_nontemporal_store(val, reinterpret_cast<S*>(run + off));
-#else
-        *reinterpret_cast<S*>(run + off) = val;
-#endif
+        store_pop<S>(run + off, val);
         run += runb;
     }
 };
@@ -325,29 +366,16 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accu
 }
 
 // ---------------------------------------------------------------------------
-// Forward update: pull gather, moments, equilibrium, BGK relaxation, store.
-// STORE_MOM additionally writes the D+2 moments of the input state
-// (delta rho or rho, U, theta - 1) for the adjoint.
-//
-// Relaxation: out = omc v + omega_eff W (dr + rho h)   (F32S)
-//             out = omc v + omega_eff W rho (1 + h)    (F64)
-// with omc + omega_eff = 1 exactly, so mass, momentum and energy are
-// conserved up to the rounding of each cell's own values.
-template <class M, class P, bool STORE_MOM>
-__global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
-void k_step(const typename P::S* __restrict__ src,
-                                                 typename P::S* __restrict__ dst, KParams k,
-                                                 typename P::S* __restrict__ mom) {
-    using S = typename P::S;
-    using R = S;
+// Moments, equilibrium and BGK relaxation of one cell's incoming values v;
+// emit(I, value) receives post-collision population I::value, in increasing
+// order.  Returns the cell's macroscopic values.
+template <class M, class P, class Emit>
+__device__ __forceinline__ Macro relax_cell(const KParams& k, const typename P::S (&v)[M::Q],
+                                            Emit&& emit) {
+    using R = typename P::S;
     constexpr int Q = M::Q;
     constexpr int G = M::G;
     constexpr int D = M::D;
-    const Cell cl = row_cell(k);
-
-    S v[Q];
-    gather<M, +1>(src, k, cl, v);
-
     using A = typename P::Acc;
     A m0 = A(0), jx = A(0), jy = A(0), jz = A(0), en = A(0);
     static_for<Q>([&](auto I) {
@@ -367,7 +395,6 @@ void k_step(const typename P::S* __restrict__ src,
     const double wr = k.omega_eff * mc.rho;
     const double wd = k.omega_eff * mc.dr;
     const R omc = R(k.omc);
-    PlaneWriter<S> out_w(dst, k, cl, Q);
 
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
@@ -386,9 +413,32 @@ void k_step(const typename P::S* __restrict__ src,
             } else {
                 out = fma(ca, h, fma(omc, v[i], ca));
             }
-            out_w.put(out);
+            emit(std::integral_constant<int, i>{}, out);
         });
     });
+    return mc;
+}
+
+// Forward update, two buffers: pull gather from src, relax, store to dst.
+// STORE_MOM additionally writes the D+2 moments of the input state
+// (delta rho or rho, U, theta - 1) for the adjoint.
+//
+// Relaxation: out = omc v + omega_eff W (dr + rho h)   (F32S)
+//             out = omc v + omega_eff W rho (1 + h)    (F64)
+// with omc + omega_eff = 1 exactly, so mass, momentum and energy are
+// conserved up to the rounding of each cell's own values.
+template <class M, class P, bool STORE_MOM>
+__global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
+void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst, KParams k,
+            typename P::S* __restrict__ mom) {
+    using S = typename P::S;
+    constexpr int D = M::D;
+    const Cell cl = row_cell(k);
+
+    S v[M::Q];
+    gather<M, +1>(src, k, cl, v);
+    PlaneWriter<S> out_w(dst, k, cl, M::Q);
+    const Macro mc = relax_cell<M, P>(k, v, [&](auto, S val) { out_w.put(val); });
 
     if constexpr (STORE_MOM) {
         if (cl.active) {
@@ -401,6 +451,46 @@ void k_step(const typename P::S* __restrict__ src,
     }
 }
 
+// Forward update in place on one buffer (AA pattern).  The buffer holds the
+// post-collision state f* of the current step in one of two forms:
+//   swapped : f*_i(x) in run opp(i) of cell x,
+//   pushed  : f*_i(x) in run i of cell x + e_i (already streamed).
+// PUSH = true  reads the swapped form: the value arriving at x along e_i is
+//              run opp(i) of cell x - e_i; it relaxes and writes f*_i(x) to
+//              run i of cell x + e_i (pushed form).
+// PUSH = false reads the pushed form: run i of cell x is the arriving value;
+//              it relaxes and writes f*_i(x) to run opp(i) of cell x
+//              (swapped form).
+// Every location is read and then written by the same thread only, so the
+// update is race-free in place.  Idle lanes of a ragged row do not store
+// (a duplicate store could overwrite a value before its reader loads it).
+template <class M, class P, bool PUSH>
+__global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
+void k_step_aa(typename P::S* f, KParams k) {
+    using S = typename P::S;
+    const Cell cl = row_cell(k);
+    const SlabAddr<M, S, char> ad(reinterpret_cast<char*>(f), k, cl);
+    S v[M::Q];
+    static_for<M::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+        if constexpr (PUSH)
+            v[i] = load_pop<S>(ad.template at<M::table.opp[i], -ex, -ey, -ez>());
+        else
+            v[i] = load_pop<S>(ad.template at<i, 0, 0, 0>());
+    });
+    relax_cell<M, P>(k, v, [&](auto I, S val) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+        if (cl.active) {
+            if constexpr (PUSH)
+                store_pop<S>(ad.template at<i, ex, ey, ez>(), val);
+            else
+                store_pop<S>(ad.template at<M::table.opp[i], 0, 0, 0>(), val);
+        }
+    });
+}
+
 // ---------------------------------------------------------------------------
 // Store f^eq(r, U, T) of one cell, computed in float64 (Formula (3)).
 template <class M, class P>
@@ -410,7 +500,7 @@ __device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const K
     const double d = T * k.invT0 - 1.0;
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
-    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
+    const PopAt<M> pa(k, c);
     static_for<M::G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
         const GCoef gc = group_coef(k, g, u2, d);
@@ -420,9 +510,9 @@ __device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const K
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double h = horner_h(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
             if constexpr (P::shifted) {
-                f[pi(i)] = static_cast<float>(w * (r - k.rho0) + w * r * h);
+                f[pa.template at<i>(k)] = static_cast<float>(w * (r - k.rho0) + w * r * h);
             } else {
-                f[pi(i)] = w * r * (1.0 + h);
+                f[pa.template at<i>(k)] = w * r * (1.0 + h);
             }
         });
     });
@@ -462,15 +552,15 @@ __global__ __launch_bounds__(kBlock) void k_set_pop(const double* __restrict__ f
                                                     typename P::S* __restrict__ f, KParams k) {
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= k.N) return;
-    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
+    const PopAt<M> pa(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int g = M::table.group[i];
         const double val = fin[static_cast<long long>(i) * k.N + c];
         if constexpr (P::shifted)
-            f[pi(i)] = static_cast<float>(val - k.W[g] * k.rho0);
+            f[pa.template at<i>(k)] = static_cast<float>(val - k.W[g] * k.rho0);
         else
-            f[pi(i)] = val;
+            f[pa.template at<i>(k)] = val;
     });
 }
 
@@ -479,11 +569,11 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(const typename P::S* __restr
                                                     double* __restrict__ fout, KParams k) {
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= k.N) return;
-    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
+    const PopAt<M> pa(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int g = M::table.group[i];
-        const double val = static_cast<double>(f[pi(i)]);
+        const double val = static_cast<double>(f[pa.template at<i>(k)]);
         fout[static_cast<long long>(i) * k.N + c] = P::shifted ? val + k.W[g] * k.rho0 : val;
     });
 }
@@ -495,12 +585,12 @@ __device__ __forceinline__ void cell_sums(const S* __restrict__ f, const KParams
     m0 = 0.0;
     j[0] = j[1] = j[2] = 0.0;
     en = 0.0;
-    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
+    const PopAt<M> pa(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
         constexpr int ee = M::table.e2[M::table.group[i]];
-        const double val = static_cast<double>(f[pi(i)]);
+        const double val = static_cast<double>(f[pa.template at<i>(k)]);
         m0 += val;
         if constexpr (ex != 0) j[0] += double(ex) * val;
         if constexpr (ey != 0) j[1] += double(ey) * val;
@@ -596,11 +686,11 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     if (c < k.N) {
         const double g = dLdrho[c];
         double m0 = 0.0;
-        const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
+        const PopAt<M> pa(k, c);
         static_for<M::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            m0 += static_cast<double>(fn[pi(i)]);
-            lam[pi(i)] = static_cast<S>(g);
+            m0 += static_cast<double>(fn[pa.template at<i>(k)]);
+            lam[pa.template at<i>(k)] = static_cast<S>(g);
         });
         const double r = P::shifted ? k.rho0 + m0 : m0;
         acc[0] = g * r;
@@ -765,7 +855,7 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
     const double d = T[c] * k.invT0 - 1.0;
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
-    const PopIdx<M::Q> pi = pop_idx<M::Q>(k, c);
+    const PopAt<M> pa(k, c);
     double sd = 0.0;
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
@@ -776,7 +866,7 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double s = edot<ex, ey, ez>(utx, uty, utz);
             const double pd = gd.c0 + s * (gd.c1 + s * gd.c2);
-            tg += static_cast<double>(lam[pi(i)]) * pd;
+            tg += static_cast<double>(lam[pa.template at<i>(k)]) * pd;
         });
         sd += k.W[g] * tg;
     });
@@ -885,6 +975,23 @@ hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, vo
                                dim3(kp.bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
                                kp, static_cast<S*>(nullptr));
         }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool push,
+                          hipStream_t s) {
+    return with_types(m, p, [&](auto M_, auto P_) {
+        using M = decltype(M_);
+        using P = decltype(P_);
+        using S = typename P::S;
+        const dim3 grid(static_cast<unsigned>(step_blocks(m, p, kp)));
+        if (push)
+            hipLaunchKernelGGL((k_step_aa<M, P, true>), grid, dim3(kp.bx), 0, s,
+                               static_cast<S*>(f), kp);
+        else
+            hipLaunchKernelGGL((k_step_aa<M, P, false>), grid, dim3(kp.bx), 0, s,
+                               static_cast<S*>(f), kp);
         return hipGetLastError();
     });
 }

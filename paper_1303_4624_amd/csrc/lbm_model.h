@@ -49,6 +49,7 @@ struct VelocityTable {
     int gstart[G_];     // first velocity of each group
     int gsize[G_];
     int e2[G_];         // |e|^2 of the group
+    int opp[Q_];        // index of the opposite velocity -e_i
     int emax;           // largest |component|
     bool ok;            // orbit sizes matched the declared group orders
 };
@@ -132,6 +133,16 @@ constexpr VelocityTable<D, Q, G> make_table(const GroupRep (&reps)[G]) {
         }
     }
     if (q != Q) t.ok = false;
+    for (int i = 0; i < Q; ++i) {
+        t.opp[i] = -1;
+        for (int j = 0; j < Q; ++j) {
+            bool neg = true;
+            for (int k = 0; k < 3; ++k)
+                if (t.e[j][k] != -t.e[i][k]) neg = false;
+            if (neg) t.opp[i] = j;
+        }
+        if (t.opp[i] < 0) t.ok = false;
+    }
     return t;
 }
 

@@ -14,6 +14,7 @@ from . import _lib as L
 
 MODELS = {"D2Q33": (2, 33), "D3Q95": (3, 95)}
 PRECISIONS = {"fp64": L.LBM_FP64, "fp32s": L.LBM_FP32_SHIFTED}
+STREAMING = {"ab": L.LBM_STREAM_AB, "aa": L.LBM_STREAM_AA}
 
 
 def _dev_bytes(nbytes: int, device) -> torch.Tensor:
@@ -32,11 +33,12 @@ class Simulation:
     extent    : (nx, ny[, nz])
     omega     : relaxation frequency
     precision : "fp64" or "fp32s" (float32 deviations from w_i rho0)
+    streaming : "ab" (two population buffers) or "aa" (one buffer, in place)
     """
 
     def __init__(self, model: str, extent: Sequence[int], omega: float,
                  precision: str = "fp64", rho0: float = 1.0, device="cuda",
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, streaming: str = "ab"):
         if model not in MODELS:
             raise ValueError(f"unknown model {model}")
         self.model = model
@@ -53,10 +55,14 @@ class Simulation:
         self.omega = float(omega)
         self.ctx = L.lbm_create(self.D, self.Q, self.e, self.w, self.c, self.extent, omega,
                                 PRECISIONS[precision], rho0, self.stream.cuda_stream)
+        if streaming not in STREAMING:
+            raise ValueError(f"unknown streaming scheme {streaming}")
+        self.streaming = streaming
+        L.lbm_set_streaming(self.ctx, STREAMING[streaming])
         pop, scr = L.lbm_workspace_bytes(self.ctx)
         self.pop_bytes = pop
         self._fa = _dev_bytes(pop, self.device)
-        self._fb = _dev_bytes(pop, self.device)
+        self._fb = _dev_bytes(pop, self.device) if streaming == "ab" else None
         self._scratch = _dev_bytes(scr, self.device)
         with torch.cuda.device(self.device):
             L.lbm_bind(self.ctx, self._fa, self._fb, self._scratch)

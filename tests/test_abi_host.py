@@ -184,3 +184,26 @@ def test_fixed_planes_validation(name):
             assert ex.value.status == want, args
     finally:
         L.lbm_destroy(ctx)
+
+
+def test_streaming_scheme_validation():
+    ctx = L.lbm_create(**_args("D3Q95", extent=[6, 4, 20]))
+    good = [1.0, 0.0, 0.0, 0.0, 1.0]
+    try:
+        with pytest.raises(L.LBMError) as ex:
+            L.lbm_set_streaming(ctx, 2)
+        assert ex.value.status == L.LBM_E_INVALID
+        L.lbm_set_streaming(ctx, L.LBM_STREAM_AA)
+        with pytest.raises(L.LBMError) as ex:
+            L.lbm_set_fixed_planes(ctx, 5, 5, good, good)
+        assert ex.value.status == L.LBM_E_UNSUPPORTED
+        L.lbm_set_fixed_planes(ctx, 0, 0)           # clearing is always allowed
+        L.lbm_set_streaming(ctx, L.LBM_STREAM_AB)
+        L.lbm_set_fixed_planes(ctx, 5, 5, good, good)
+        with pytest.raises(L.LBMError) as ex:
+            L.lbm_set_streaming(ctx, L.LBM_STREAM_AA)
+        assert ex.value.status == L.LBM_E_UNSUPPORTED
+        pop, _ = L.lbm_workspace_bytes(ctx)
+        assert pop == 95 * 6 * 4 * 20 * 8
+    finally:
+        L.lbm_destroy(ctx)
