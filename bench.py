@@ -10,8 +10,10 @@ the HIP-event duration of the timed launches, against 8 TB/s HBM; the HBM
 bytes per launch measured by rocprofv3 counters on the same kernel source),
 the CPU oracle's rate on a bounded sample, and side measurements: FP64 on
 256^3, FP32-shifted vs FP64 error after 200 steps on 256^3, D2Q33 in both
-precisions on 8192^2, the two shock tubes with held end planes, and the
-forward + adjoint cost on 128^3 x 200 steps with checkpoints every 20.
+precisions on 8192^2, in-place (AA) streaming on 384^3 and on 768^3 (a grid
+whose two-buffer state would not fit in HBM), the two shock tubes with held
+end planes, and the forward + adjoint cost on 128^3 x 200 steps with
+checkpoints every 20.
 """
 from __future__ import annotations
 
@@ -120,6 +122,31 @@ def run_fp64_and_error(extent, omega, steps_time, steps_err, model="D3Q95"):
     del fields
     torch.cuda.empty_cache()
     return out, err
+
+
+def run_aa(extent, steps, tile=None):
+    """D3Q95 FP32-shifted with in-place (AA) streaming: one population buffer."""
+    import torch
+    from paper_1303_4624_amd import Simulation
+    from synth_inputs import smooth_ic, tiled_smooth_ic
+    rho, U, th = smooth_ic(extent) if tile is None else tiled_smooth_ic(extent, tile)
+    sim = Simulation("D3Q95", extent, 1.8, precision="fp32s", streaming="aa")
+    sim.init_fields(rho, U, th * sim.T0)
+    del rho, U, th
+    m0 = sim.conservation()[0]
+    wall, ev = timed_steps(sim, steps, 4)
+    m1 = sim.conservation()[0]
+    N, pb = sim.N, sim.pop_bytes
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    mlups = N * steps / ev / 1e6
+    return {"grid": list(extent), "steps": steps, "mlups": round(mlups, 2),
+            "ms_per_step": round(ev / steps * 1e3, 4),
+            "roofline_frac": round(mlups * 760 / 1e3 / HBM_PEAK_GBS, 4),
+            "population_GB": round(pb / 1e9, 2), "two_buffer_GB": round(2 * pb / 1e9, 2),
+            "mass_rel_change": abs(m1 - m0) / abs(m0),
+            "ic": "smooth" if tile is None else f"smooth {tile[0]}^3 tile repeated"}
 
 
 def run_tube(wname, precision):
@@ -325,6 +352,9 @@ def main():
             d["roofline_frac"] = round(d["mlups"] * bpc / 1e3 / HBM_PEAK_GBS, 4)
             out[f"d2q33_{prec}_8192sq"] = d
         out["d2q33_fp32s_vs_fp64_8192sq"] = err
+        log("[bench] in-place (AA) streaming, 384^3 and 768^3")
+        out["aa_fp32s_384c"] = run_aa((384, 384, 384), 100)
+        out["aa_fp32s_768c"] = run_aa((768, 768, 768), 30, tile=(192, 192, 192))
         log("[bench] shock tubes with held end planes")
         for wname in ("d3q95_11x11x800_tube", "d2q33_11x800_tube"):
             for prec in ("fp64", "fp32s"):

