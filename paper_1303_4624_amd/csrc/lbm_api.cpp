@@ -67,8 +67,12 @@ int fail_hip(lbm_ctx* ctx, hipError_t e, const char* what) {
 
 size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
+// Elements between two population runs of a grid row.
+long long run_stride(const lbm_ctx* ctx) { return ctx->extent[0] + lbm::kRunPad; }
+
 size_t pop_bytes(const lbm_ctx* ctx) {
-    return static_cast<size_t>(ctx->N) * ctx->Q * elem_bytes(ctx->prec);
+    return static_cast<size_t>(ctx->N / ctx->extent[0]) * run_stride(ctx) * ctx->Q *
+           elem_bytes(ctx->prec);
 }
 
 size_t scratch_bytes(const lbm_ctx* ctx) {
@@ -119,6 +123,7 @@ void fill_kparams(lbm_ctx* ctx) {
     k.nx = static_cast<int>(ctx->extent[0]);
     k.ny = static_cast<int>(ctx->extent[1]);
     k.nz = ctx->D == 3 ? static_cast<int>(ctx->extent[2]) : 1;
+    k.rs = static_cast<int>(run_stride(ctx));
     k.N = ctx->N;
     const long long rows = static_cast<long long>(k.ny) * k.nz;
     const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads(ctx->prec));
@@ -248,7 +253,7 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
         return fail(nullptr, LBM_E_INVALID, "grid too large for one launch");
     // The kernels address one slab of the slowest axis (all populations of a
     // z-plane in 3D, of a row in 2D) with 32-bit byte offsets.
-    const long long slab = (D == 3 ? extent[0] * extent[1] : extent[0]) * Q *
+    const long long slab = (extent[0] + lbm::kRunPad) * (D == 3 ? extent[1] : 1) * Q *
                            (precision == LBM_FP64 ? 8LL : 4LL);
     if (slab >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID,

@@ -17,6 +17,12 @@ namespace lbm {
 // the X-only parts of its coefficients are precomputed here:
 //   K1 = (X - D)/2, K2 = (D + 2 - X)/4, K3 = (X^2 - 2(D + 2)X + D(D + 2))/8,
 //   K4 = (X - D - 2)/2, K5 = (X - D - 4)/4.
+// Elements added to every population run of a row (run stride = nx + pad).
+#ifndef LBM_RUN_PAD
+#define LBM_RUN_PAD 0
+#endif
+constexpr int kRunPad = LBM_RUN_PAD;
+
 // Storage forms of the population buffer (see the kernels' PopAt).
 constexpr int kFormAB = 0;        // two buffers: run i of cell c
 constexpr int kFormSwapped = 1;   // in place, after an even number of steps: run opp(i) of c
@@ -25,6 +31,7 @@ constexpr int kFormPushed = 2;    // in place, after an odd number of steps: run
 struct KParams {
     int nx, ny, nz;           // nz = 1 in 2D
     int form;                 // storage form of the state the kernel reads or writes
+    int rs;                   // run stride: elements between two population runs of a row
     int chunks;               // blocks per grid row (x direction)
     int bx;                   // threads per block (multiple of 64)
     long long N;              // cells

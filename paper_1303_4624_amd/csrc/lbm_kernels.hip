@@ -132,7 +132,8 @@ struct Cell {
 
 // Storage layout of the populations: the Q populations of one grid row
 // (fixed y[, z]) are contiguous, population-major inside the row, so
-// element (i, c) with c = row*nx + x sits at (row*Q + i)*nx + x.  A step
+// element (i, c) with c = row*nx + x sits at (row*Q + i)*rs + x, rs >= nx
+// the run stride (KParams::rs).  A step
 // then writes one contiguous run per row and reads Q runs from the few
 // source rows around it.
 //
@@ -159,10 +160,10 @@ struct PopAt {
             const long long yr = wrap_idx(y + ey, k.ny);
             const long long r = (M::D == 3) ? static_cast<long long>(wrap_idx(z + ez, k.nz)) * k.ny + yr
                                             : yr;
-            return (r * Q + i) * k.nx + xr;
+            return (r * Q + i) * k.rs + xr;
         }
         const int slot = (k.form == kFormSwapped) ? M::table.opp[i] : i;
-        return (row * Q + slot) * k.nx + x;
+        return (row * Q + slot) * k.rs + x;
     }
 };
 
@@ -203,7 +204,7 @@ struct SlabAddr {
     unsigned xb[kW], yb[kW];
     B* sb[kW];
     __device__ __forceinline__ SlabAddr(B* base, const KParams& k, const Cell& cl) {
-        runb = static_cast<unsigned>(k.nx) * static_cast<unsigned>(sizeof(S));
+        runb = static_cast<unsigned>(k.rs) * static_cast<unsigned>(sizeof(S));
         const unsigned rowb = runb * static_cast<unsigned>(M::Q);
         static_for<kW>([&](auto DI) {
             constexpr int d = decltype(DI)::value - kMaxDisp;   // table entry d: cell at -d
@@ -273,8 +274,8 @@ struct PlaneWriter {
     unsigned off;
     __device__ __forceinline__ PlaneWriter(S* dst, const KParams& k, const Cell& cl, int Q)
         : run(reinterpret_cast<char*>(dst) +
-              static_cast<unsigned long long>(cl.row) * Q * k.nx * sizeof(S)),
-          runb(static_cast<unsigned long long>(k.nx) * sizeof(S)),
+              static_cast<unsigned long long>(cl.row) * Q * k.rs * sizeof(S)),
+          runb(static_cast<unsigned long long>(k.rs) * sizeof(S)),
           off(static_cast<unsigned>(cl.x) * static_cast<unsigned>(sizeof(S))) {}
     __device__ __forceinline__ void put(S val) {
         store_pop<S>(run + off, val);
