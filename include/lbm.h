@@ -109,6 +109,41 @@ typedef enum lbm_precision {
 int lbm_velocity_set(int D, int Q, int32_t* e, double* w, double* c);
 
 /*
+ * lbm_equation_count - Omega(m, D) of Formula (8): the number of equations
+ * Formula (5) gives up to order 2m in D dimensions, one per partition of
+ * q <= m into at most D parts (Table 1).  0 <= m <= 16, 1 <= D <= 8.
+ */
+int lbm_equation_count(int m, int D, int* count);
+
+/*
+ * lbm_model_build - construct an on-lattice model from a choice of groups
+ * (the method of the counting section, Formulas (5) and (8)-(10)).
+ *   D, m      : dimension (1, 2 or 3) and order of accuracy (1..8); the
+ *               equations are Formula (5) for every even multi-index of
+ *               order <= 2m.
+ *   G, reps   : number of groups and host int32[G][D] representatives; each
+ *               group is the orbit of its representative under coordinate
+ *               permutations and sign changes (components in [-64, 64]).
+ *               Formula (10) must hold: G + 1 = Omega(m, D).
+ *   w_guess   : host double[G] initial group weights, or NULL for the least
+ *               squares weights at c_guess; c_guess > 0 initial speed.
+ *   q_cap     : rows available in e and group.
+ * Outputs (any may be NULL): e int32[Q][D] in canonical order (groups in
+ * the given order, ascending tuples inside a group), group int32[Q],
+ * w double[Q] per velocity, c, Q, residual (largest |Formula (5) residual|
+ * at the float64 result).  The square system is solved by Newton in
+ * binary128 and rounded once; with the representatives and printed values
+ * of Table 2 or 3 the result equals lbm_velocity_set bit for bit.
+ * Returns LBM_E_UNSUPPORTED for other D, LBM_E_INVALID for a system that is
+ * not square, repeated groups, no convergence, a non-positive weight or c,
+ * or q_cap < Q (Q is still reported in the last case).  Only the D2Q33 and
+ * D3Q95 models have kernels (lbm_create).
+ */
+int lbm_model_build(int D, int m, int G, const int32_t* reps, const double* w_guess,
+                    double c_guess, int q_cap, int32_t* e, int32_t* group, double* w, double* c,
+                    int* Q, double* residual);
+
+/*
  * lbm_create - validate a model and a grid and make a context.
  *
  *   out       : receives the context (host memory owned by the library,

@@ -30,7 +30,7 @@ LBM_STREAM_AA = 1
 LBM_MAX_Q = 95
 
 EXPORTED = [
-    "lbm_velocity_set", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
+    "lbm_velocity_set", "lbm_equation_count", "lbm_model_build", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments",
     "lbm_conservation", "lbm_set_fixed_planes", "lbm_set_streaming", "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_str",
@@ -55,6 +55,9 @@ _psz = ctypes.POINTER(ctypes.c_size_t)
 
 _SIGS = {
     "lbm_velocity_set": (_c.c_int, [_c.c_int, _c.c_int, _pi32, _pd, _pd]),
+    "lbm_equation_count": (_c.c_int, [_c.c_int, _c.c_int, ctypes.POINTER(_c.c_int)]),
+    "lbm_model_build": (_c.c_int, [_c.c_int, _c.c_int, _c.c_int, _pi32, _pd, _c.c_double, _c.c_int,
+                                   _pi32, _pi32, _pd, _pd, ctypes.POINTER(_c.c_int), _pd]),
     "lbm_create": (_c.c_int, [ctypes.POINTER(_vp), _c.c_int, _c.c_int, _pi32, _pd, _c.c_double,
                               _pi64, _c.c_double, _c.c_int, _c.c_double, _vp]),
     "lbm_workspace_bytes": (_c.c_int, [_vp, _psz, _psz]),
@@ -132,6 +135,35 @@ def lbm_velocity_set(D: int, Q: int) -> Tuple[np.ndarray, np.ndarray, float]:
                                     ctypes.byref(c))
     _check(st, "lbm_velocity_set")
     return e, w, float(c.value)
+
+
+def lbm_equation_count(m: int, D: int) -> int:
+    n = ctypes.c_int(0)
+    _check(library().lbm_equation_count(int(m), int(D), ctypes.byref(n)), "lbm_equation_count")
+    return n.value
+
+
+def lbm_model_build(D: int, m: int, reps, c_guess: float, w_guess=None):
+    """(e int32[Q, D], group int32[Q], w float64[Q], c, residual) of the model
+    whose groups are the orbits of ``reps`` (int[G][D])."""
+    reps = np.ascontiguousarray(reps, dtype=np.int32).reshape(-1, D)
+    G = reps.shape[0]
+    wg = None if w_guess is None else np.ascontiguousarray(w_guess, dtype=np.float64)
+    if wg is not None and wg.size != G:
+        raise ValueError("w_guess needs one value per group")
+    cap = G * (48 if D == 3 else 8)
+    e = np.zeros((cap, D), dtype=np.int32)
+    grp = np.zeros(cap, dtype=np.int32)
+    w = np.zeros(cap, dtype=np.float64)
+    c, Q, res = ctypes.c_double(0), ctypes.c_int(0), ctypes.c_double(0)
+    st = library().lbm_model_build(D, int(m), G, reps.ctypes.data_as(_pi32),
+                                   None if wg is None else wg.ctypes.data_as(_pd),
+                                   float(c_guess), cap, e.ctypes.data_as(_pi32),
+                                   grp.ctypes.data_as(_pi32), w.ctypes.data_as(_pd),
+                                   ctypes.byref(c), ctypes.byref(Q), ctypes.byref(res))
+    _check(st, "lbm_model_build")
+    q = Q.value
+    return e[:q].copy(), grp[:q].copy(), w[:q].copy(), c.value, res.value
 
 
 def lbm_create(D: int, Q: int, e, w, c: float, extent: Sequence[int], omega: float,

@@ -200,6 +200,50 @@ LBM_API int lbm_velocity_set(int D, int Q, int32_t* e, double* w, double* c) {
     return LBM_OK;
 }
 
+LBM_API int lbm_equation_count(int m, int D, int* count) {
+    if (!count) return fail(nullptr, LBM_E_INVALID, "count is NULL");
+    if (m < 0 || m > 16 || D < 1 || D > 8)
+        return fail(nullptr, LBM_E_INVALID, "need 0 <= m <= 16 and 1 <= D <= 8");
+    *count = lbm::equation_count(m, D);
+    g_err.clear();
+    return LBM_OK;
+}
+
+LBM_API int lbm_model_build(int D, int m, int G, const int32_t* reps, const double* w_guess,
+                            double c_guess, int q_cap, int32_t* e, int32_t* group, double* w,
+                            double* c, int* Q, double* residual) {
+    if (D < 1 || D > 3) return fail(nullptr, LBM_E_UNSUPPORTED, "D must be 1, 2 or 3");
+    if (m < 1 || m > 8 || G < 1 || !reps || !(c_guess > 0.0) || !std::isfinite(c_guess))
+        return fail(nullptr, LBM_E_INVALID, "need 1 <= m <= 8, G >= 1, reps and c_guess > 0");
+    if (w_guess)
+        for (int g = 0; g < G; ++g)
+            if (!std::isfinite(w_guess[g]))
+                return fail(nullptr, LBM_E_INVALID, "w_guess has a non-finite value");
+    lbm::BuiltModel bm;
+    std::string err;
+    if (!lbm::model_build(D, m, G, reps, w_guess, c_guess, bm, err))
+        return fail(nullptr, LBM_E_INVALID, err);
+    if (Q) *Q = bm.Q;
+    for (int g = 0; g < G; ++g)
+        if (!(bm.W[g] > 0.0))
+            return fail(nullptr, LBM_E_INVALID,
+                        "the solution has a non-positive weight (group " + std::to_string(g) + ")");
+    if (!(bm.c > 0.0)) return fail(nullptr, LBM_E_INVALID, "the solution has c <= 0");
+    if (bm.Q > q_cap)
+        return fail(nullptr, LBM_E_INVALID,
+                    "q_cap is smaller than the number of velocities " + std::to_string(bm.Q));
+    for (int i = 0; i < bm.Q; ++i) {
+        if (e)
+            for (int k = 0; k < D; ++k) e[i * D + k] = bm.e[i][k];
+        if (group) group[i] = bm.group[i];
+        if (w) w[i] = bm.W[bm.group[i]];
+    }
+    if (c) *c = bm.c;
+    if (residual) *residual = bm.residual;
+    g_err.clear();
+    return LBM_OK;
+}
+
 LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const double* w,
                        double c, const int64_t* extent, double omega, int precision,
                        double rho0, void* stream) {

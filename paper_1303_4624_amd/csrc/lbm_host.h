@@ -1,8 +1,10 @@
 // lbm_host.h - host-side model queries used by the C-ABI layer.
 #pragma once
 
+#include <array>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "lbm_model.h"
 
@@ -21,5 +23,23 @@ bool model_matches(ModelId m, const int32_t* e);
 double model_residual(ModelId m, const double* W, double c);
 // Newton solution of Formula (5) for the group weights and c.
 bool model_solve(ModelId m, double* W, double* c, std::string& err);
+
+// Number of equations of Formula (5) up to order 2m in D dimensions
+// (Omega(m, D) of Formula (8)).
+int equation_count(int m, int D);
+
+// A model built from arbitrary group representatives.
+struct BuiltModel {
+    int D = 0, Q = 0, G = 0;
+    std::vector<std::array<int, 3>> e;
+    std::vector<int> group;
+    std::vector<double> W;
+    double c = 0, residual = 0;
+};
+// Orbits of reps (int32[G][D]) and the Newton solution of Formula (5) up to
+// order 2m from the given guesses (w_guess may be NULL: least squares at
+// c_guess).  Fails unless G + 1 = Omega(m, D) (Formula (10)).
+bool model_build(int D, int m, int G, const int32_t* reps, const double* w_guess, double c_guess,
+                 BuiltModel& out, std::string& err);
 
 }  // namespace lbm

@@ -7,6 +7,8 @@
 // condition number of about 3e6, so a float64 solve leaves errors near 1e-11
 // in the weights, a small but systematic change of the model.  In binary128
 // the result rounds to the nearest float64 of the exact root.
+#include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <string>
@@ -33,11 +35,12 @@ ModelView view(ModelId m) {
 }
 
 // Exponent tuples (a_1 >= ... >= a_D, all even) of the equations of Formula (5)
-// up to order 2m = 8: one per partition of q <= 4 into at most D parts.
-void equation_exponents(int D, std::vector<std::vector<int>>& out) {
+// up to order 2m: one per partition of q <= m into at most D parts
+// (Formula (8)).
+void equation_exponents(int D, int m, std::vector<std::vector<int>>& out) {
     out.clear();
     std::vector<int> cur(D, 0);
-    // enumerate non-increasing tuples p_1 >= p_2 >= ... >= p_D >= 0, sum <= 4
+    // enumerate non-increasing tuples p_1 >= p_2 >= ... >= p_D >= 0, sum <= m
     auto rec = [&](auto&& self, int pos, int maxpart, int rest) -> void {
         if (pos == D) {
             std::vector<int> a(D);
@@ -50,7 +53,7 @@ void equation_exponents(int D, std::vector<std::vector<int>>& out) {
             self(self, pos + 1, p, rest - p);
         }
     };
-    rec(rec, 0, 4, 4);
+    rec(rec, 0, m, m);
 }
 
 // (a - 1)!! / 2^(a/2) for even a: the 1D Gaussian moment normalised to unit mass.
@@ -60,6 +63,70 @@ double gauss_moment_1d(int a) {
     return v / std::ldexp(1.0, a / 2);
 }
 
+// Velocity list of a model: groups in order, each the orbit of its
+// representative under coordinate permutations and sign changes, sorted
+// ascending inside the group.
+struct OrbitModel {
+    int D = 0, Q = 0, G = 0;
+    std::vector<std::array<int, 3>> e;
+    std::vector<int> group;
+};
+
+OrbitModel builtin_model(ModelId m) {
+    const ModelView v = view(m);
+    OrbitModel om;
+    om.D = v.D;
+    om.Q = v.Q;
+    om.G = v.G;
+    for (int i = 0; i < v.Q; ++i) {
+        om.e.push_back({v.e[i][0], v.e[i][1], v.e[i][2]});
+        om.group.push_back(v.group[i]);
+    }
+    return om;
+}
+
+bool make_orbits(int D, int G, const int32_t* reps, OrbitModel& om, std::string& err) {
+    om = OrbitModel{};
+    om.D = D;
+    om.G = G;
+    std::vector<std::array<int, 3>> keys;   // sorted |components|, one per orbit
+    for (int g = 0; g < G; ++g) {
+        std::array<int, 3> r{0, 0, 0};
+        for (int k = 0; k < D; ++k) {
+            r[k] = reps[g * D + k];
+            if (r[k] < -64 || r[k] > 64) {
+                err = "representative components must lie in [-64, 64]";
+                return false;
+            }
+        }
+        std::array<int, 3> key{0, 0, 0};
+        for (int k = 0; k < D; ++k) key[k] = r[k] < 0 ? -r[k] : r[k];
+        std::sort(key.begin(), key.begin() + D);
+        for (const auto& kk : keys)
+            if (kk == key) {
+                err = "two representatives generate the same group";
+                return false;
+            }
+        keys.push_back(key);
+        std::array<int, 3> perm{0, 1, 2};
+        std::vector<std::array<int, 3>> orb;
+        do {
+            for (int s = 0; s < (1 << D); ++s) {
+                std::array<int, 3> v{0, 0, 0};
+                for (int k = 0; k < D; ++k) v[k] = ((s >> k) & 1) ? -r[perm[k]] : r[perm[k]];
+                if (std::find(orb.begin(), orb.end(), v) == orb.end()) orb.push_back(v);
+            }
+        } while (std::next_permutation(perm.begin(), perm.begin() + D));
+        std::sort(orb.begin(), orb.end());
+        for (const auto& v : orb) {
+            om.e.push_back(v);
+            om.group.push_back(g);
+        }
+    }
+    om.Q = static_cast<int>(om.e.size());
+    return true;
+}
+
 struct System {
     int G = 0;
     std::vector<std::vector<double>> B;   // B[k][g] = sum over group g of e^a
@@ -67,26 +134,25 @@ struct System {
     std::vector<double> rhs;
 };
 
-System build_system(ModelId m) {
-    const ModelView v = view(m);
+System build_system(const OrbitModel& om, int m) {
     System s;
-    s.G = v.G;
+    s.G = om.G;
     std::vector<std::vector<int>> ex;
-    equation_exponents(v.D, ex);
+    equation_exponents(om.D, m, ex);
     for (const auto& a : ex) {
-        std::vector<double> row(v.G, 0.0);
+        std::vector<double> row(om.G, 0.0);
         int ord = 0;
         double r = 1.0;
-        for (int k = 0; k < v.D; ++k) {
+        for (int k = 0; k < om.D; ++k) {
             ord += a[k];
             r *= gauss_moment_1d(a[k]);
         }
-        for (int i = 0; i < v.Q; ++i) {
+        for (int i = 0; i < om.Q; ++i) {
             double mono = 1.0;
-            for (int k = 0; k < v.D; ++k) {
-                for (int p = 0; p < a[k]; ++p) mono *= v.e[i][k];
+            for (int k = 0; k < om.D; ++k) {
+                for (int p = 0; p < a[k]; ++p) mono *= om.e[i][k];
             }
-            row[v.group[i]] += mono;
+            row[om.group[i]] += mono;
         }
         s.B.push_back(row);
         s.order.push_back(ord);
@@ -94,6 +160,8 @@ System build_system(ModelId m) {
     }
     return s;
 }
+
+System build_system(ModelId m) { return build_system(builtin_model(m), 4); }
 
 void residual_and_jacobian(const System& s, const std::vector<double>& W, double c,
                            std::vector<double>& F, std::vector<std::vector<double>>* J) {
@@ -112,6 +180,80 @@ void residual_and_jacobian(const System& s, const std::vector<double>& W, double
         F[k] = cp * acc - s.rhs[k];
         if (J) (*J)[k][s.G] = dacc;
     }
+}
+
+double max_residual(const System& s, const std::vector<double>& W, double c) {
+    std::vector<double> F;
+    residual_and_jacobian(s, W, c, F, nullptr);
+    double worst = 0.0;
+    for (double f : F) worst = std::fmax(worst, std::fabs(f));
+    return worst;
+}
+
+using quad = __float128;
+
+quad qabs(quad a) { return a < 0 ? -a : a; }
+
+// Solve the n x n system A x = b (A has n + 1 columns, b in the last) by
+// Gaussian elimination with partial pivoting, in binary128.
+bool solve_dense(std::vector<std::vector<quad>>& A, std::vector<quad>& x) {
+    const int n = static_cast<int>(A.size());
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (qabs(A[r][col]) > qabs(A[piv][col])) piv = r;
+        if (A[piv][col] == 0) return false;
+        std::swap(A[piv], A[col]);
+        for (int r = col + 1; r < n; ++r) {
+            const quad f = A[r][col] / A[col][col];
+            for (int cc = col; cc <= n; ++cc) A[r][cc] -= f * A[col][cc];
+        }
+    }
+    x.assign(n, 0);
+    for (int r = n - 1; r >= 0; --r) {
+        quad t = A[r][n];
+        for (int cc = r + 1; cc < n; ++cc) t -= A[r][cc] * x[cc];
+        x[r] = t / A[r][r];
+    }
+    return true;
+}
+
+// Newton on the square system F(W, c) = 0 of Formula (5), in binary128,
+// from x = (W_1..W_G, c).
+bool newton(const System& s, std::vector<quad>& x, std::string& err) {
+    const int n = static_cast<int>(s.rhs.size());
+    const int G = s.G;
+    for (int it = 0; it < 80; ++it) {
+        std::vector<std::vector<quad>> A(n, std::vector<quad>(n + 1, 0));
+        for (int k = 0; k < n; ++k) {
+            quad cp = 1, dcp = 0;
+            for (int p = 0; p < s.order[k]; ++p) {
+                dcp = dcp * x[G] + cp;
+                cp *= x[G];
+            }
+            quad acc = 0;
+            for (int g = 0; g < G; ++g) {
+                acc += x[g] * static_cast<quad>(s.B[k][g]);
+                A[k][g] = cp * static_cast<quad>(s.B[k][g]);
+            }
+            A[k][G] = dcp * acc;
+            A[k][n] = -(cp * acc - static_cast<quad>(s.rhs[k]));
+        }
+        std::vector<quad> dx;
+        if (!solve_dense(A, dx)) {
+            err = "singular Jacobian in the weight solve";
+            return false;
+        }
+        quad rel = 0;
+        for (int k = 0; k < n; ++k) {
+            x[k] += dx[k];
+            const quad r = qabs(dx[k]) / qabs(x[k]);
+            if (r > rel) rel = r;
+        }
+        if (rel < static_cast<quad>(1e-30)) return true;
+    }
+    err = "Newton iteration for the weights did not converge";
+    return false;
 }
 
 }  // namespace
@@ -147,82 +289,77 @@ bool model_matches(ModelId m, const int32_t* e) {
 
 double model_residual(ModelId m, const double* W, double c) {
     const System s = build_system(m);
-    std::vector<double> Wv(W, W + s.G), F;
-    residual_and_jacobian(s, Wv, c, F, nullptr);
-    double worst = 0.0;
-    for (double f : F) worst = std::fmax(worst, std::fabs(f));
-    return worst;
+    return max_residual(s, std::vector<double>(W, W + s.G), c);
 }
 
 bool model_solve(ModelId m, double* W, double* c, std::string& err) {
-    using q = __float128;
     const ModelView v = view(m);
     const System s = build_system(m);
-    const int n = static_cast<int>(s.rhs.size());
-    if (n != v.G + 1) {
+    if (static_cast<int>(s.rhs.size()) != v.G + 1) {
         err = "weight system is not square";
         return false;
     }
-    std::vector<q> x(v.G + 1);
+    std::vector<quad> x(v.G + 1);
     for (int g = 0; g < v.G; ++g) x[g] = v.printedW[g];
     x[v.G] = v.printedC;
-    auto qabs = [](q a) { return a < 0 ? -a : a; };
-    bool converged = false;
-    for (int it = 0; it < 80; ++it) {
-        // residual and Jacobian in binary128
-        std::vector<std::vector<q>> A(n, std::vector<q>(n + 1, 0));
-        for (int k = 0; k < n; ++k) {
-            q cp = 1, dcp = 0;
-            for (int p = 0; p < s.order[k]; ++p) {
-                dcp = dcp * x[v.G] + cp;
-                cp *= x[v.G];
-            }
-            q acc = 0;
-            for (int g = 0; g < v.G; ++g) {
-                acc += x[g] * static_cast<q>(s.B[k][g]);
-                A[k][g] = cp * static_cast<q>(s.B[k][g]);
-            }
-            A[k][v.G] = dcp * acc;
-            A[k][n] = -(cp * acc - static_cast<q>(s.rhs[k]));
-        }
-        // Gaussian elimination with partial pivoting
-        for (int col = 0; col < n; ++col) {
-            int piv = col;
-            for (int r = col + 1; r < n; ++r)
-                if (qabs(A[r][col]) > qabs(A[piv][col])) piv = r;
-            if (A[piv][col] == 0) {
-                err = "singular Jacobian in the weight solve";
-                return false;
-            }
-            std::swap(A[piv], A[col]);
-            for (int r = col + 1; r < n; ++r) {
-                const q f = A[r][col] / A[col][col];
-                for (int cc = col; cc <= n; ++cc) A[r][cc] -= f * A[col][cc];
-            }
-        }
-        std::vector<q> dx(n, 0);
-        for (int r = n - 1; r >= 0; --r) {
-            q t = A[r][n];
-            for (int cc = r + 1; cc < n; ++cc) t -= A[r][cc] * dx[cc];
-            dx[r] = t / A[r][r];
-        }
-        q rel = 0;
-        for (int k = 0; k < n; ++k) {
-            x[k] += dx[k];
-            const q r = qabs(dx[k]) / qabs(x[k]);
-            if (r > rel) rel = r;
-        }
-        if (rel < static_cast<q>(1e-30)) {
-            converged = true;
-            break;
-        }
-    }
-    if (!converged) {
-        err = "Newton iteration for the weights did not converge";
-        return false;
-    }
+    if (!newton(s, x, err)) return false;
     for (int g = 0; g < v.G; ++g) W[g] = static_cast<double>(x[g]);
     *c = static_cast<double>(x[v.G]);
+    return true;
+}
+
+int equation_count(int m, int D) {
+    std::vector<std::vector<int>> ex;
+    equation_exponents(D, m, ex);
+    return static_cast<int>(ex.size());
+}
+
+bool model_build(int D, int m, int G, const int32_t* reps, const double* w_guess, double c_guess,
+                 BuiltModel& out, std::string& err) {
+    OrbitModel om;
+    if (!make_orbits(D, G, reps, om, err)) return false;
+    const System s = build_system(om, m);
+    const int n = static_cast<int>(s.rhs.size());
+    if (n != G + 1) {
+        err = "Formula (10) needs G + 1 = Omega(m, D) = " + std::to_string(n) + " unknowns, got " +
+              std::to_string(G + 1);
+        return false;
+    }
+    std::vector<quad> x(G + 1);
+    x[G] = c_guess;
+    if (w_guess) {
+        for (int g = 0; g < G; ++g) x[g] = w_guess[g];
+    } else {
+        // least-squares weights at c_guess: (A^T A) W = A^T rhs, A = c^|a| B
+        std::vector<std::vector<quad>> A(n, std::vector<quad>(G));
+        for (int k = 0; k < n; ++k) {
+            quad cp = 1;
+            for (int p = 0; p < s.order[k]; ++p) cp *= x[G];
+            for (int g = 0; g < G; ++g) A[k][g] = cp * static_cast<quad>(s.B[k][g]);
+        }
+        std::vector<std::vector<quad>> N(G, std::vector<quad>(G + 1, 0));
+        for (int i = 0; i < G; ++i) {
+            for (int j = 0; j < G; ++j)
+                for (int k = 0; k < n; ++k) N[i][j] += A[k][i] * A[k][j];
+            for (int k = 0; k < n; ++k) N[i][G] += A[k][i] * static_cast<quad>(s.rhs[k]);
+        }
+        std::vector<quad> w0;
+        if (!solve_dense(N, w0)) {
+            err = "singular least-squares system for the initial weights";
+            return false;
+        }
+        for (int g = 0; g < G; ++g) x[g] = w0[g];
+    }
+    if (!newton(s, x, err)) return false;
+    out.D = D;
+    out.Q = om.Q;
+    out.G = G;
+    out.e = om.e;
+    out.group = om.group;
+    out.W.assign(G, 0.0);
+    for (int g = 0; g < G; ++g) out.W[g] = static_cast<double>(x[g]);
+    out.c = static_cast<double>(x[G]);
+    out.residual = max_residual(s, out.W, out.c);
     return true;
 }
 
