@@ -25,9 +25,12 @@
  *  - Grid: extents (nx, ny[, nz]), every axis periodic, N = nx*ny[*nz] cells,
  *    linear cell index x + nx*(y + ny*z) (x fastest).
  *  - Populations in the bound buffers, checkpoints and adjoint workspace:
- *    row-blocked, i.e. the Q populations of one grid row (fixed y[, z]) are
- *    contiguous and population-major inside the row: population i of cell
- *    c = x + nx*r (r = y + ny*z the row) is element (r*Q + i)*nx + x.  In
+ *    row-blocked, i.e. the Q populations of a group of g consecutive grid
+ *    rows are contiguous and population-major inside the group, the g rows
+ *    of one population adjacent (g = 2 in 3D when ny is even, else 1):
+ *    population i of cell (x, y, z) is element
+ *    ((z*ny/g + y/g)*Q*g + i*g + y%g)*nx + x.  The layout is internal to the
+ *    library (sizes from lbm_workspace_bytes).  In
  *    LBM_FP64 each element is the double f*_i.  In LBM_FP32_SHIFTED each
  *    element is the float g_i = f*_i - w_i*rho0.  lbm_set_populations and
  *    lbm_get_populations exchange float64 f* in the order [Q][N] (element

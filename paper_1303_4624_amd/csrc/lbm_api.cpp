@@ -124,6 +124,7 @@ void fill_kparams(lbm_ctx* ctx) {
     k.ny = static_cast<int>(ctx->extent[1]);
     k.nz = ctx->D == 3 ? static_cast<int>(ctx->extent[2]) : 1;
     k.rs = static_cast<int>(run_stride(ctx));
+    k.rg = (ctx->D == 3 && k.ny % lbm::kRowGroup3D == 0) ? lbm::kRowGroup3D : 1;
     k.N = ctx->N;
     const long long rows = static_cast<long long>(k.ny) * k.nz;
     const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads(ctx->prec));

@@ -65,6 +65,10 @@ namespace {
 // The pushed stores of the AA kernel start at x + e_x, off the 128-byte
 // line grid; plain stores let L2 merge the partial lines of neighbouring
 // waves before they reach HBM (measured 5 % faster than non-temporal).
+// Dynamic LDS reserved per block of the step kernels (limits blocks per CU).
+#ifndef LBM_STEP_DYN_LDS
+#define LBM_STEP_DYN_LDS 0
+#endif
 #ifndef LBM_AA_NT_PUSH
 #define LBM_AA_NT_PUSH 0
 #endif
@@ -130,23 +134,31 @@ struct Cell {
     long long c;        // linear cell index
 };
 
-// Storage layout of the populations: the Q populations of one grid row
-// (fixed y[, z]) are contiguous, population-major inside the row, so
-// element (i, c) with c = row*nx + x sits at (row*Q + i)*rs + x, rs >= nx
-// the run stride (KParams::rs).  A step
-// then writes one contiguous run per row and reads Q runs from the few
-// source rows around it.
+// Storage layout of the populations: the Q populations of a group of rg
+// consecutive grid rows (fixed z; rg = 1 in 2D) are contiguous,
+// population-major, the rg rows of one population adjacent: population i
+// of cell (x, y, z) sits at row_base(y, z) + i*rg*rs + x, rs >= nx the run
+// stride (KParams::rs, KParams::rg).  A step then writes contiguous runs per
+// row and reads Q runs from the few source rows around it.
 //
 // Where population i of cell c is stored depends on the form of the state
 // (KParams::form): kFormAB, run i of cell c; kFormSwapped (in-place AA
 // pattern after an even number of steps), run opp(i) of cell c;
 // kFormPushed (AA after an odd number), run i of cell c + e_i.
+// Element offset of the first population run of grid row (y, z): rows are
+// taken in groups of rg consecutive y (same z) whose runs interleave, so a
+// population run of a group is rg*rs elements long.
+__device__ __forceinline__ long long row_base(const KParams& k, int Q, int y, int z) {
+    const int gy = y / k.rg, ry = y - gy * k.rg;
+    return (static_cast<long long>(z) * k.ny * Q + static_cast<long long>(gy) * Q * k.rg + ry) *
+           k.rs;
+}
+
 template <class M>
 struct PopAt {
-    long long row;
     int x, y, z;
     __device__ __forceinline__ PopAt(const KParams& k, long long c) {
-        row = c / k.nx;
+        const long long row = c / k.nx;
         x = static_cast<int>(c - row * k.nx);
         y = static_cast<int>(row % k.ny);
         z = static_cast<int>(row / k.ny);
@@ -154,16 +166,16 @@ struct PopAt {
     template <int i>
     __device__ __forceinline__ long long at(const KParams& k) const {
         constexpr int Q = M::Q;
+        const long long pstride = static_cast<long long>(k.rg) * k.rs;
         if (k.form == kFormPushed) {
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-            const long long xr = wrap_idx(x + ex, k.nx);
-            const long long yr = wrap_idx(y + ey, k.ny);
-            const long long r = (M::D == 3) ? static_cast<long long>(wrap_idx(z + ez, k.nz)) * k.ny + yr
-                                            : yr;
-            return (r * Q + i) * k.rs + xr;
+            const int xr = wrap_idx(x + ex, k.nx);
+            const int yr = wrap_idx(y + ey, k.ny);
+            const int zr = (M::D == 3) ? wrap_idx(z + ez, k.nz) : 0;
+            return row_base(k, Q, yr, zr) + i * pstride + xr;
         }
         const int slot = (k.form == kFormSwapped) ? M::table.opp[i] : i;
-        return (row * Q + slot) * k.rs + x;
+        return row_base(k, Q, y, z) + slot * pstride + x;
     }
 };
 
@@ -204,19 +216,23 @@ struct SlabAddr {
     unsigned xb[kW], yb[kW];
     B* sb[kW];
     __device__ __forceinline__ SlabAddr(B* base, const KParams& k, const Cell& cl) {
-        runb = static_cast<unsigned>(k.rs) * static_cast<unsigned>(sizeof(S));
-        const unsigned rowb = runb * static_cast<unsigned>(M::Q);
+        const unsigned rsb = static_cast<unsigned>(k.rs) * static_cast<unsigned>(sizeof(S));
+        runb = rsb * static_cast<unsigned>(k.rg);
+        const unsigned groupb = runb * static_cast<unsigned>(M::Q);   // one row group
         static_for<kW>([&](auto DI) {
             constexpr int d = decltype(DI)::value - kMaxDisp;   // table entry d: cell at -d
             xb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.x - d, k.nx)) * sizeof(S);
+            const int yr = wrap_idx(cl.y - d, k.ny);
+            const int gy = yr / k.rg, ry = yr - gy * k.rg;
+            const unsigned inslab = static_cast<unsigned>(gy) * groupb + static_cast<unsigned>(ry) * rsb;
             if constexpr (M::D == 3) {
-                yb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.y - d, k.ny)) * rowb;
+                yb[d + kMaxDisp] = inslab;
                 sb[d + kMaxDisp] = base + static_cast<unsigned long long>(wrap_idx(cl.z - d, k.nz)) *
-                                              (static_cast<unsigned long long>(rowb) * k.ny);
+                                              (static_cast<unsigned long long>(rsb) * M::Q * k.ny);
             } else {
                 yb[d + kMaxDisp] = 0u;
-                sb[d + kMaxDisp] =
-                    base + static_cast<unsigned long long>(wrap_idx(cl.y - d, k.ny)) * rowb;
+                sb[d + kMaxDisp] = base + static_cast<unsigned long long>(gy) * groupb +
+                                   static_cast<unsigned long long>(ry) * rsb;
             }
         });
     }
@@ -274,8 +290,8 @@ struct PlaneWriter {
     unsigned off;
     __device__ __forceinline__ PlaneWriter(S* dst, const KParams& k, const Cell& cl, int Q)
         : run(reinterpret_cast<char*>(dst) +
-              static_cast<unsigned long long>(cl.row) * Q * k.rs * sizeof(S)),
-          runb(static_cast<unsigned long long>(k.rs) * sizeof(S)),
+              static_cast<unsigned long long>(row_base(k, Q, cl.y, cl.z)) * sizeof(S)),
+          runb(static_cast<unsigned long long>(k.rs) * k.rg * sizeof(S)),
           off(static_cast<unsigned>(cl.x) * static_cast<unsigned>(sizeof(S))) {}
     __device__ __forceinline__ void put(S val) {
         store_pop<S>(run + off, val);
@@ -977,11 +993,11 @@ hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, vo
         using S = typename P::S;
         if (mom_out) {
             hipLaunchKernelGGL((k_step<M, P, true>), dim3(static_cast<unsigned>(blocks)),
-                               dim3(kp.bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
+                               dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<const S*>(src), static_cast<S*>(dst),
                                kp, static_cast<S*>(mom_out));
         } else {
             hipLaunchKernelGGL((k_step<M, P, false>), dim3(static_cast<unsigned>(blocks)),
-                               dim3(kp.bx), 0, s, static_cast<const S*>(src), static_cast<S*>(dst),
+                               dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<const S*>(src), static_cast<S*>(dst),
                                kp, static_cast<S*>(nullptr));
         }
         return hipGetLastError();
@@ -996,10 +1012,10 @@ hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool pu
         using S = typename P::S;
         const dim3 grid(static_cast<unsigned>(step_blocks(m, p, kp)));
         if (push)
-            hipLaunchKernelGGL((k_step_aa<M, P, true>), grid, dim3(kp.bx), 0, s,
+            hipLaunchKernelGGL((k_step_aa<M, P, true>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
                                static_cast<S*>(f), kp);
         else
-            hipLaunchKernelGGL((k_step_aa<M, P, false>), grid, dim3(kp.bx), 0, s,
+            hipLaunchKernelGGL((k_step_aa<M, P, false>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
                                static_cast<S*>(f), kp);
         return hipGetLastError();
     });
