@@ -1,21 +1,27 @@
 // lbm_kernels.hip - HIP kernels for CDNA4 (gfx950) of the thermal lattice
 // Boltzmann update with the D2Q33 / D3Q95 on-lattice models.
 //
-// Data layout: structure of arrays, population i of cell c at i*N + c, cells
-// x-fastest.  One thread owns one cell.  Every population read is a contiguous
-// run of a grid row (neighbouring threads read neighbouring x), so the
-// gather f_i(x - e_i) is coalesced; the x-wrap of the periodic grid is folded
-// into the per-lane index, the y/z-wrap into a wave-uniform row offset.
+// Data layout: row-blocked.  The Q populations of a group of consecutive
+// grid rows are contiguous, population-major (see PopAt / row_base), cells
+// x-fastest.  One thread owns one cell and a block one grid row (or a chunk
+// of it).  Every population read is a contiguous run of a source row
+// (neighbouring threads read neighbouring x), so the gather f_i(x - e_i) is
+// coalesced; the x-wrap of the periodic grid is folded into a per-lane
+// offset, the y/z-wrap into wave-uniform slab bases and row offsets.
 //
 // Precision variants:
 //   F64  : f_i stored and computed in float64.
-//   F32S : g_i = f_i - w_i rho0 stored in float32.  The per-velocity work
-//          (sums, polynomial, relaxation, store) is float32; the per-cell
-//          scalars (rho, U, theta) and the per-group coefficients are formed in
-//          float64 and rounded once per cell.  Rounding the model constants
-//          themselves to float32 would change the model by ~1e-8 in every cell
-//          and step alike; per-cell rounding only adds noise.  The O(1) part
-//          w_i rho0 never enters float32 arithmetic.
+//   F32S : g_i = f_i - w_i rho0 stored in float32.  The moment sums are
+//          accumulated in float64; the per-cell scalars (rho, U, theta) and
+//          the per-group coefficients are formed in float64 and rounded once
+//          per cell; the polynomial, relaxation and store are float32.
+//          Rounding the model constants themselves to float32 would change
+//          the model by ~1e-8 in every cell and step alike; per-cell rounding
+//          only adds noise.  The O(1) part w_i rho0 never enters float32
+//          arithmetic.
+//
+// Streaming: two buffers (k_step: pull from one, store to the other) or one
+// buffer updated in place (k_step_aa, the AA pattern).
 //
 // Equilibrium: the 4th-order Hermite expansion of the Maxwellian, written as
 // a polynomial in s = xi_i . u_hat for each symmetry group (|e_i|^2 is
