@@ -13,9 +13,11 @@
  * Formula (2), order N = m = 4 as the paragraph after Formula (8) requires),
  * and the per-cell moments rho, U, T of the Maxwellian.  Around the update it
  * provides initialisation from macroscopic fields, moment output, global
- * conservation sums, checkpointed runs and a hand-written adjoint that gives
- * gradients of a loss on the final density with respect to the initial
- * temperature field and omega.
+ * conservation sums, the fixed end planes of the shock-tube experiment,
+ * two-buffer or in-place (AA pattern) streaming, checkpointed runs, a
+ * hand-written adjoint that gives gradients of a loss on the final density
+ * with respect to the initial temperature field and omega, and a general
+ * constructor of on-lattice models (Formulas (5)-(10)).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -29,8 +31,10 @@
  *    rows are contiguous and population-major inside the group, the g rows
  *    of one population adjacent (g = 2 in 3D when ny is even, else 1):
  *    population i of cell (x, y, z) is element
- *    ((z*ny/g + y/g)*Q*g + i*g + y%g)*nx + x.  The layout is internal to the
- *    library (sizes from lbm_workspace_bytes).  In
+ *    ((z*ny/g + y/g)*Q*g + i*g + y%g)*nx + x (two-buffer streaming; with
+ *    LBM_STREAM_AA the slot of a value alternates, see lbm_set_streaming).
+ *    The layout is internal to the library (sizes from
+ *    lbm_workspace_bytes).  In
  *    LBM_FP64 each element is the double f*_i.  In LBM_FP32_SHIFTED each
  *    element is the float g_i = f*_i - w_i*rho0.  lbm_set_populations and
  *    lbm_get_populations exchange float64 f* in the order [Q][N] (element
@@ -48,8 +52,9 @@
  *    Theta = 2 k_B T0 / m_g and v_i = c e_i).
  *  - Memory: the library allocates no device memory.  Population buffers,
  *    scratch, checkpoints, workspaces and fields are owned by the caller
- *    (e.g. torch tensors); the library never frees them.  Device pointers
- *    must be 256-byte aligned and stay valid while the context uses them.
+ *    (e.g. torch tensors); the library never frees them.  Buffers given to
+ *    lbm_bind must be 256-byte aligned, other device arrays 8-byte aligned;
+ *    all must stay valid while the context uses them.
  *  - Asynchrony: kernels run on the stream given to lbm_create, in order.
  *    Functions that return host values (lbm_conservation, lbm_adjoint's
  *    omega gradient) synchronise that stream.
