@@ -163,7 +163,8 @@ int lbm_model_build(int D, int m, int G, const int32_t* reps, const double* w_gu
  *               summing to 1 within 1e-12.
  *   c         : speed of the model; Formula (5) must hold at (w, c) with
  *               residual <= 1e-10, else LBM_E_INVALID.
- *   extent    : host int64[D] = {nx, ny[, nz]}, each >= 1 and <= 2^24; the
+ *   extent    : host int64[D] = {nx, ny[, nz]}, each >= 1 and <= 2^24,
+ *               N < 2^31 cells (more than 288 GB of populations); the
  *               populations of one slab of the slowest axis (nx*ny*Q
  *               elements in 3D, nx*Q in 2D) must stay below 4 GiB.
  *   omega     : relaxation frequency of the update rule, 0 <= omega < 2.

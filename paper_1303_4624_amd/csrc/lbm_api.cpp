@@ -124,7 +124,9 @@ void fill_kparams(lbm_ctx* ctx) {
     k.ny = static_cast<int>(ctx->extent[1]);
     k.nz = ctx->D == 3 ? static_cast<int>(ctx->extent[2]) : 1;
     k.rs = static_cast<int>(run_stride(ctx));
-    k.rg = (ctx->D == 3 && k.ny % lbm::kRowGroup3D == 0) ? lbm::kRowGroup3D : 1;
+    const bool grouped = ctx->D == 3 && k.ny % lbm::kRowGroup3D == 0;
+    k.rg_shift = grouped ? lbm::kRowGroup3DShift : 0;
+    k.rg = 1 << k.rg_shift;
     k.N = ctx->N;
     const long long rows = static_cast<long long>(k.ny) * k.nz;
     const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads(ctx->prec));
@@ -288,7 +290,8 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
         if (extent[k] < 1) return fail(nullptr, LBM_E_INVALID, "extents must be >= 1");
         if (extent[k] > (1LL << 24)) return fail(nullptr, LBM_E_INVALID, "extent too large");
         N *= extent[k];
-        if (N > (1LL << 40)) return fail(nullptr, LBM_E_INVALID, "grid too large");
+        if (N >= (1LL << 31))
+            return fail(nullptr, LBM_E_INVALID, "grid too large: at most 2^31 - 1 cells");
     }
     const long long rows = N / extent[0];
     const lbm::RowLaunch rl =

@@ -23,14 +23,16 @@ namespace lbm {
 #endif
 constexpr int kRunPad = LBM_RUN_PAD;
 
-// Rows (consecutive y, same z) whose population runs are interleaved in 3D,
+// Rows (consecutive y, same z) whose population runs are interleaved in 3D
+// (a power of two),
 // when ny is a multiple of it (else 1); 2D rows are long enough alone.
 // Measured on D3Q95: 2 rows +0.7 % (FP32-shifted 384^3) and +1.5 % (FP64
 // 256^3); on D2Q33 8192^2 grouping lost 3 % (2 rows) to 13 % (8 rows).
-#ifndef LBM_ROW_GROUP
-#define LBM_ROW_GROUP 2
+#ifndef LBM_ROW_GROUP_SHIFT
+#define LBM_ROW_GROUP_SHIFT 1
 #endif
-constexpr int kRowGroup3D = LBM_ROW_GROUP;
+constexpr int kRowGroup3DShift = LBM_ROW_GROUP_SHIFT;
+constexpr int kRowGroup3D = 1 << kRowGroup3DShift;
 
 // Storage forms of the population buffer (see the kernels' PopAt).
 constexpr int kFormAB = 0;        // two buffers: run i of cell c
@@ -41,7 +43,8 @@ struct KParams {
     int nx, ny, nz;           // nz = 1 in 2D
     int form;                 // storage form of the state the kernel reads or writes
     int rs;                   // run stride: elements between two population runs of a row
-    int rg;                   // rows per group (consecutive y sharing interleaved runs)
+    int rg;                   // rows per group (consecutive y sharing interleaved runs), 1 or 2
+    int rg_shift;             // log2(rg)
     int chunks;               // blocks per grid row (x direction)
     int bx;                   // threads per block (multiple of 64)
     long long N;              // cells

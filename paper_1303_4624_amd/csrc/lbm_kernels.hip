@@ -62,8 +62,10 @@ namespace {
 #ifndef LBM_ADJ_SCHED_BARRIER
 #define LBM_ADJ_SCHED_BARRIER 0
 #endif
+// Occupancy target of the adjoint kernel: 3 waves per SIMD keeps it at
+// <= 168 VGPRs without spills (4 % faster than letting it grow to 256).
 #ifndef LBM_ADJ_WAVES
-#define LBM_ADJ_WAVES 1
+#define LBM_ADJ_WAVES 3
 #endif
 #ifndef LBM_F32_WAVES
 #define LBM_F32_WAVES 1
@@ -155,33 +157,63 @@ struct Cell {
 // taken in groups of rg consecutive y (same z) whose runs interleave, so a
 // population run of a group is rg*rs elements long.
 __device__ __forceinline__ long long row_base(const KParams& k, int Q, int y, int z) {
-    const int gy = y / k.rg, ry = y - gy * k.rg;
+    const int gy = y >> k.rg_shift;
+    const int ry = y - (gy << k.rg_shift);
     return (static_cast<long long>(z) * k.ny * Q + static_cast<long long>(gy) * Q * k.rg + ry) *
            k.rs;
 }
 
-template <class M>
+// Element index of population i of cell c in storage form FORM (a
+// compile-time copy of KParams::form, see with_form).  The per-cell work
+// (divisions, and the neighbour offsets of the pushed form) is done once in
+// the constructor; at<i>() is a few adds.  Cell indices fit in 32 bits
+// (N < 2^31 is checked on the host).
+__device__ __forceinline__ void cell_xyz(const KParams& k, long long c, int& x, int& y, int& z) {
+    const unsigned cu = static_cast<unsigned>(c);
+    const unsigned row = cu / static_cast<unsigned>(k.nx);
+    x = static_cast<int>(cu - row * static_cast<unsigned>(k.nx));
+    y = static_cast<int>(row % static_cast<unsigned>(k.ny));
+    z = static_cast<int>(row / static_cast<unsigned>(k.ny));
+}
+
+template <class M, int FORM>
 struct PopAt {
-    int x, y, z;
+    long long base;              // own cell, run 0
+    long long pstride;           // elements between two population runs
     __device__ __forceinline__ PopAt(const KParams& k, long long c) {
-        const long long row = c / k.nx;
-        x = static_cast<int>(c - row * k.nx);
-        y = static_cast<int>(row % k.ny);
-        z = static_cast<int>(row / k.ny);
+        int x, y, z;
+        cell_xyz(k, c, x, y, z);
+        pstride = static_cast<long long>(k.rg) * k.rs;
+        base = row_base(k, M::Q, y, z) + x;
     }
     template <int i>
-    __device__ __forceinline__ long long at(const KParams& k) const {
-        constexpr int Q = M::Q;
-        const long long pstride = static_cast<long long>(k.rg) * k.rs;
-        if (k.form == kFormPushed) {
-            constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-            const int xr = wrap_idx(x + ex, k.nx);
-            const int yr = wrap_idx(y + ey, k.ny);
-            const int zr = (M::D == 3) ? wrap_idx(z + ez, k.nz) : 0;
-            return row_base(k, Q, yr, zr) + i * pstride + xr;
-        }
-        const int slot = (k.form == kFormSwapped) ? M::table.opp[i] : i;
-        return row_base(k, Q, y, z) + slot * pstride + x;
+    __device__ __forceinline__ long long at() const {
+        constexpr int slot = (FORM == kFormSwapped) ? M::table.opp[i] : i;
+        return base + slot * pstride;
+    }
+};
+
+template <class M>
+struct PopAt<M, kFormPushed> {
+    long long pstride;
+    long long zo[kW], yo[kW];    // row offsets of the cells at +d
+    int xo[kW];
+    __device__ __forceinline__ PopAt(const KParams& k, long long c) {
+        int x, y, z;
+        cell_xyz(k, c, x, y, z);
+        pstride = static_cast<long long>(k.rg) * k.rs;
+        static_for<kW>([&](auto DI) {
+            constexpr int d = decltype(DI)::value - kMaxDisp;
+            xo[d + kMaxDisp] = wrap_idx(x + d, k.nx);
+            yo[d + kMaxDisp] = row_base(k, M::Q, wrap_idx(y + d, k.ny), 0);
+            zo[d + kMaxDisp] =
+                (M::D == 3) ? static_cast<long long>(wrap_idx(z + d, k.nz)) * k.ny * M::Q * k.rs : 0;
+        });
+    }
+    template <int i>
+    __device__ __forceinline__ long long at() const {
+        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+        return zo[ez + kMaxDisp] + yo[ey + kMaxDisp] + i * pstride + xo[ex + kMaxDisp];
     }
 };
 
@@ -229,7 +261,7 @@ struct SlabAddr {
             constexpr int d = decltype(DI)::value - kMaxDisp;   // table entry d: cell at -d
             xb[d + kMaxDisp] = static_cast<unsigned>(wrap_idx(cl.x - d, k.nx)) * sizeof(S);
             const int yr = wrap_idx(cl.y - d, k.ny);
-            const int gy = yr / k.rg, ry = yr - gy * k.rg;
+            const int gy = yr >> k.rg_shift, ry = yr - (gy << k.rg_shift);
             const unsigned inslab = static_cast<unsigned>(gy) * groupb + static_cast<unsigned>(ry) * rsb;
             if constexpr (M::D == 3) {
                 yb[d + kMaxDisp] = inslab;
@@ -524,14 +556,14 @@ void k_step_aa(typename P::S* f, KParams k) {
 
 // ---------------------------------------------------------------------------
 // Store f^eq(r, U, T) of one cell, computed in float64 (Formula (3)).
-template <class M, class P>
+template <class M, class P, int FORM>
 __device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const KParams& k,
                                           long long c, double r, double ux, double uy,
                                           double uz, double T) {
     const double d = T * k.invT0 - 1.0;
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
-    const PopAt<M> pa(k, c);
+    const PopAt<M, FORM> pa(k, c);
     static_for<M::G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
         const GCoef gc = group_coef(k, g, u2, d);
@@ -541,23 +573,24 @@ __device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const K
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double h = horner_h(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
             if constexpr (P::shifted) {
-                f[pa.template at<i>(k)] = static_cast<float>(w * (r - k.rho0) + w * r * h);
+                f[pa.template at<i>()] = static_cast<float>(w * (r - k.rho0) + w * r * h);
             } else {
-                f[pa.template at<i>(k)] = w * r * (1.0 + h);
+                f[pa.template at<i>()] = w * r * (1.0 + h);
             }
         });
     });
 }
 
 // f = f^eq(rho, U, T) from float64 fields.
-template <class M, class P>
+template <class M, class P, int FORM>
 __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ rho,
                                                  const double* __restrict__ U,
                                                  const double* __restrict__ T,
                                                  typename P::S* __restrict__ f, KParams k) {
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= k.N) return;
-    store_feq<M, P>(f, k, c, rho[c], U[c], U[k.N + c], (M::D == 3) ? U[2 * k.N + c] : 0.0, T[c]);
+    store_feq<M, P, FORM>(f, k, c, rho[c], U[c], U[k.N + c], (M::D == 3) ? U[2 * k.N + c] : 0.0,
+                          T[c]);
 }
 
 // Hold the first n_lo and the last n_hi planes of the slowest axis at the
@@ -574,54 +607,54 @@ __global__ __launch_bounds__(kBlock) void k_fix_planes(typename P::S* __restrict
     const bool is_lo = t < cells_lo;
     const long long c = is_lo ? t : static_cast<long long>(nlast - n_hi) * plane + (t - cells_lo);
     const FixedState& st = is_lo ? lo : hi;
-    store_feq<M, P>(f, k, c, st.rho, st.U[0], st.U[1], st.U[2], st.T);
+    store_feq<M, P, kFormAB>(f, k, c, st.rho, st.U[0], st.U[1], st.U[2], st.T);
 }
 
 // Copy float64 f[Q][N] into storage, and back.
-template <class M, class P>
+template <class M, class P, int FORM>
 __global__ __launch_bounds__(kBlock) void k_set_pop(const double* __restrict__ fin,
                                                     typename P::S* __restrict__ f, KParams k) {
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= k.N) return;
-    const PopAt<M> pa(k, c);
+    const PopAt<M, FORM> pa(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int g = M::table.group[i];
         const double val = fin[static_cast<long long>(i) * k.N + c];
         if constexpr (P::shifted)
-            f[pa.template at<i>(k)] = static_cast<float>(val - k.W[g] * k.rho0);
+            f[pa.template at<i>()] = static_cast<float>(val - k.W[g] * k.rho0);
         else
-            f[pa.template at<i>(k)] = val;
+            f[pa.template at<i>()] = val;
     });
 }
 
-template <class M, class P>
+template <class M, class P, int FORM>
 __global__ __launch_bounds__(kBlock) void k_get_pop(const typename P::S* __restrict__ f,
                                                     double* __restrict__ fout, KParams k) {
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= k.N) return;
-    const PopAt<M> pa(k, c);
+    const PopAt<M, FORM> pa(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int g = M::table.group[i];
-        const double val = static_cast<double>(f[pa.template at<i>(k)]);
+        const double val = static_cast<double>(f[pa.template at<i>()]);
         fout[static_cast<long long>(i) * k.N + c] = P::shifted ? val + k.W[g] * k.rho0 : val;
     });
 }
 
 // Raw float64 sums of one cell: sum v, sum v e, sum v |e|^2 of the stored values.
-template <class M, class S>
+template <class M, int FORM, class S>
 __device__ __forceinline__ void cell_sums(const S* __restrict__ f, const KParams& k, long long c,
                                           double& m0, double (&j)[3], double& en) {
     m0 = 0.0;
     j[0] = j[1] = j[2] = 0.0;
     en = 0.0;
-    const PopAt<M> pa(k, c);
+    const PopAt<M, FORM> pa(k, c);
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
         constexpr int ee = M::table.e2[M::table.group[i]];
-        const double val = static_cast<double>(f[pa.template at<i>(k)]);
+        const double val = static_cast<double>(f[pa.template at<i>()]);
         m0 += val;
         if constexpr (ex != 0) j[0] += double(ex) * val;
         if constexpr (ey != 0) j[1] += double(ey) * val;
@@ -630,7 +663,7 @@ __device__ __forceinline__ void cell_sums(const S* __restrict__ f, const KParams
     });
 }
 
-template <class M, class P>
+template <class M, class P, int FORM>
 __global__ __launch_bounds__(kBlock) void k_moments(const typename P::S* __restrict__ f,
                                                     double* __restrict__ rho, double* __restrict__ U,
                                                     double* __restrict__ T, KParams k) {
@@ -638,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const typename P::S* __restr
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= k.N) return;
     double m0, j[3], en;
-    cell_sums<M>(f, k, c, m0, j, en);
+    cell_sums<M, FORM>(f, k, c, m0, j, en);
     double r, d;
     double u[3];
     if constexpr (P::shifted) {
@@ -660,7 +693,7 @@ __global__ __launch_bounds__(kBlock) void k_moments(const typename P::S* __restr
 }
 
 // Conservation sums of the stored values, grid-stride, fixed order.
-template <class M, class P>
+template <class M, class P, int FORM>
 __global__ __launch_bounds__(kBlock) void k_conservation(const typename P::S* __restrict__ f,
                                                          KParams k, double* __restrict__ partials) {
     constexpr int D = M::D;
@@ -670,7 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_conservation(const typename P::S* __
     for (long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; c < k.N;
          c += stride) {
         double m0, j[3], en;
-        cell_sums<M>(f, k, c, m0, j, en);
+        cell_sums<M, FORM>(f, k, c, m0, j, en);
         acc[0] += m0;
         for (int a = 0; a < D; ++a) acc[1 + a] += j[a];
         acc[D + 1] += 0.5 * en;
@@ -717,11 +750,11 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     if (c < k.N) {
         const double g = dLdrho[c];
         double m0 = 0.0;
-        const PopAt<M> pa(k, c);
+        const PopAt<M, kFormAB> pa(k, c);
         static_for<M::Q>([&](auto I) {
             constexpr int i = decltype(I)::value;
-            m0 += static_cast<double>(fn[pa.template at<i>(k)]);
-            lam[pa.template at<i>(k)] = static_cast<S>(g);
+            m0 += static_cast<double>(fn[pa.template at<i>()]);
+            lam[pa.template at<i>()] = static_cast<S>(g);
         });
         const double r = P::shifted ? k.rho0 + m0 : m0;
         acc[0] = g * r;
@@ -886,7 +919,7 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
     const double d = T[c] * k.invT0 - 1.0;
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
-    const PopAt<M> pa(k, c);
+    const PopAt<M, kFormAB> pa(k, c);
     double sd = 0.0;
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
@@ -897,7 +930,7 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double s = edot<ex, ey, ez>(utx, uty, utz);
             const double pd = gd.c0 + s * (gd.c1 + s * gd.c2);
-            tg += static_cast<double>(lam[pa.template at<i>(k)]) * pd;
+            tg += static_cast<double>(lam[pa.template at<i>()]) * pd;
         });
         sd += k.W[g] * tg;
     });
@@ -943,14 +976,31 @@ long long step_blocks(ModelId, Prec, const KParams& kp) {
     return static_cast<long long>(kp.ny) * kp.nz * kp.chunks;
 }
 
+// Calls f with std::integral_constant<int, kp.form>.
+template <class F>
+hipError_t with_form(const KParams& kp, F&& f) {
+    if (kp.form == kFormPushed) return f(std::integral_constant<int, kFormPushed>{});
+    if (kp.form == kFormSwapped) return f(std::integral_constant<int, kFormSwapped>{});
+    return f(std::integral_constant<int, kFormAB>{});
+}
+
+// Same for the forms a kernel that writes a whole state starts from.
+template <class F>
+hipError_t with_initial_form(const KParams& kp, F&& f) {
+    if (kp.form == kFormSwapped) return f(std::integral_constant<int, kFormSwapped>{});
+    return f(std::integral_constant<int, kFormAB>{});
+}
+
 hipError_t launch_init(ModelId m, Prec p, const KParams& kp, const double* rho, const double* U,
                        const double* T, void* f, hipStream_t s) {
     return with_types(m, p, [&](auto M_, auto P_) {
         using M = decltype(M_);
         using P = decltype(P_);
-        hipLaunchKernelGGL((k_init<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s, rho, U, T,
-                           static_cast<typename P::S*>(f), kp);
-        return hipGetLastError();
+        return with_initial_form(kp, [&](auto F) {
+            hipLaunchKernelGGL((k_init<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                               dim3(kBlock), 0, s, rho, U, T, static_cast<typename P::S*>(f), kp);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -973,9 +1023,11 @@ hipError_t launch_set_pop(ModelId m, Prec p, const KParams& kp, const double* fi
     return with_types(m, p, [&](auto M_, auto P_) {
         using M = decltype(M_);
         using P = decltype(P_);
-        hipLaunchKernelGGL((k_set_pop<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s, fin,
-                           static_cast<typename P::S*>(f), kp);
-        return hipGetLastError();
+        return with_initial_form(kp, [&](auto F) {
+            hipLaunchKernelGGL((k_set_pop<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                               dim3(kBlock), 0, s, fin, static_cast<typename P::S*>(f), kp);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -984,9 +1036,11 @@ hipError_t launch_get_pop(ModelId m, Prec p, const KParams& kp, const void* f, d
     return with_types(m, p, [&](auto M_, auto P_) {
         using M = decltype(M_);
         using P = decltype(P_);
-        hipLaunchKernelGGL((k_get_pop<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s,
-                           static_cast<const typename P::S*>(f), fout, kp);
-        return hipGetLastError();
+        return with_form(kp, [&](auto F) {
+            hipLaunchKernelGGL((k_get_pop<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                               dim3(kBlock), 0, s, static_cast<const typename P::S*>(f), fout, kp);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -1032,9 +1086,12 @@ hipError_t launch_moments(ModelId m, Prec p, const KParams& kp, const void* f, d
     return with_types(m, p, [&](auto M_, auto P_) {
         using M = decltype(M_);
         using P = decltype(P_);
-        hipLaunchKernelGGL((k_moments<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s,
-                           static_cast<const typename P::S*>(f), rho, U, T, kp);
-        return hipGetLastError();
+        return with_form(kp, [&](auto F) {
+            hipLaunchKernelGGL((k_moments<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                               dim3(kBlock), 0, s, static_cast<const typename P::S*>(f), rho, U,
+                               T, kp);
+            return hipGetLastError();
+        });
     });
 }
 
@@ -1045,9 +1102,11 @@ hipError_t launch_conservation(ModelId m, Prec p, const KParams& kp, const void*
     hipError_t e = with_types(m, p, [&](auto M_, auto P_) {
         using M = decltype(M_);
         using P = decltype(P_);
-        hipLaunchKernelGGL((k_conservation<M, P>), dim3(nb), dim3(kBlock), 0, s,
-                           static_cast<const typename P::S*>(f), kp, partials);
-        return hipGetLastError();
+        return with_form(kp, [&](auto F) {
+            hipLaunchKernelGGL((k_conservation<M, P, decltype(F)::value>), dim3(nb), dim3(kBlock),
+                               0, s, static_cast<const typename P::S*>(f), kp, partials);
+            return hipGetLastError();
+        });
     });
     if (e != hipSuccess) return e;
     return launch_sum_partials(partials, nb, D + 2, D + 2, out, s);
