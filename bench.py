@@ -261,6 +261,28 @@ def cpu_oracle_baseline(extent=(64, 64, 64), steps=20):
                       f"omega 1.8, smooth seeded IC ({dt:.1f} s)"}
 
 
+def cpu_oracle_adjoint_baseline(extent=(32, 32, 32), steps=12):
+    """The oracle's gradient (float64 autograd through the forward run) on a
+    bounded sample: cell updates of forward + backward per second."""
+    import numpy as np
+    import torch
+    from oracle import lbm as olbm, velocity_sets as ovs
+    from synth_inputs import smooth_ic, target_theta
+    threads = min(16, os.cpu_count() or 1)
+    torch.set_num_threads(threads)
+    v = ovs.velocity_set("D3Q95")
+    rho, U, th = smooth_ic(extent)
+    target = np.asarray(rho) * (1 + 0.001 * target_theta(extent))
+    t0 = time.perf_counter()
+    olbm.loss_and_grad(v, rho, U, th * v.T0, 1.4, steps, target)
+    dt = time.perf_counter() - t0
+    cells = int(np.prod(extent))
+    return {"value": cells * steps / dt / 1e6, "unit": "MLUPS (forward + adjoint)",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"D3Q95 FP64 {extent[0]}^3, {steps} steps, autograd gradient of "
+                      f"sum (rho_n - rho*)^2 w.r.t. T_init and omega ({dt:.1f} s)"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +388,8 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_oracle_baseline()
+        if not args.no_extras:
+            out["cpu_baseline_fwd_adjoint"] = cpu_oracle_adjoint_baseline()
     print(json.dumps(out), flush=True)
 
 
