@@ -207,3 +207,19 @@ def test_streaming_scheme_validation():
         assert pop == 95 * 6 * 4 * 20 * 8
     finally:
         L.lbm_destroy(ctx)
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    # The package has no CPU fallback: without liblbm.so every call raises.
+    import subprocess
+    import sys
+    code = ("import paper_1303_4624_amd._lib as L\n"
+            "L.LIB_PATH = '/nonexistent/liblbm.so'\n"
+            "from paper_1303_4624_amd import Simulation\n"
+            "try:\n"
+            "    Simulation('D3Q95', (4, 4, 4), 1.2)\n"
+            "except RuntimeError as ex:\n"
+            "    print('raised:', ex)\n")
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
+                         timeout=120, cwd=ROOT)
+    assert "raised:" in res.stdout and "no CPU fallback" in res.stdout, res.stdout + res.stderr
