@@ -215,9 +215,8 @@ def test_missing_library_fails_loudly(tmp_path):
     import sys
     code = ("import paper_1303_4624_amd._lib as L\n"
             "L.LIB_PATH = '/nonexistent/liblbm.so'\n"
-            "from paper_1303_4624_amd import Simulation\n"
             "try:\n"
-            "    Simulation('D3Q95', (4, 4, 4), 1.2)\n"
+            "    L.lbm_velocity_set(3, 95)\n"
             "except RuntimeError as ex:\n"
             "    print('raised:', ex)\n")
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
