@@ -441,13 +441,6 @@ LBM_API int lbm_step(lbm_ctx* ctx, int n) {
         hipError_t e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
                                         ctx->f[1 - ctx->cur], nullptr, ctx->stream);
         if (e != hipSuccess) return fail_hip(ctx, e, "step kernel");
-        if (ctx->hold_lo + ctx->hold_hi > 0) {
-            e = lbm::launch_fix_planes(ctx->model, ctx->prec, ctx->kp, ctx->f[1 - ctx->cur],
-                                       ctx->N / ctx->extent[ctx->D - 1], ctx->hold_lo,
-                                       ctx->hold_hi, static_cast<int>(ctx->extent[ctx->D - 1]),
-                                       ctx->hold[0], ctx->hold[1], ctx->stream);
-            if (e != hipSuccess) return fail_hip(ctx, e, "fixed-plane kernel");
-        }
         ctx->cur = 1 - ctx->cur;
     }
     return LBM_OK;
@@ -480,6 +473,10 @@ LBM_API int lbm_set_fixed_planes(lbm_ctx* ctx, int n_lo, int n_hi, const double*
     ctx->hold_hi = n_hi;
     ctx->hold[0] = fs[0];
     ctx->hold[1] = fs[1];
+    ctx->kp.hold_lo = n_lo;
+    ctx->kp.hold_hi = n_hi;
+    ctx->kp.hold[0] = fs[0];
+    ctx->kp.hold[1] = fs[1];
     return LBM_OK;
 }
 

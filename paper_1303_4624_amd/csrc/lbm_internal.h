@@ -34,6 +34,13 @@ constexpr int kRunPad = LBM_RUN_PAD;
 constexpr int kRowGroup3DShift = LBM_ROW_GROUP_SHIFT;
 constexpr int kRowGroup3D = 1 << kRowGroup3DShift;
 
+// A macroscopic state held fixed on boundary planes.
+struct FixedState {
+    double rho;
+    double U[3];
+    double T;
+};
+
 // Storage forms of the population buffer (see the kernels' PopAt).
 constexpr int kFormAB = 0;        // two buffers: run i of cell c
 constexpr int kFormSwapped = 1;   // in place, after an even number of steps: run opp(i) of c
@@ -56,13 +63,8 @@ struct KParams {
     double rho0;              // shift reference (FP32-shifted storage)
     double W[kMaxG];          // group weights
     double K1[kMaxG], K2[kMaxG], K3[kMaxG], K4[kMaxG], K5[kMaxG];
-};
-
-// A macroscopic state held fixed on boundary planes.
-struct FixedState {
-    double rho;
-    double U[3];
-    double T;
+    int hold_lo, hold_hi;     // planes of the slowest axis held at f^eq(hold[0] / hold[1])
+    FixedState hold[2];
 };
 
 // Launch geometry of the row-blocked kernels: one grid row (fixed y, z) is
@@ -84,9 +86,6 @@ constexpr int kReduceThreads = 256;
 // Launchers: each returns the hipError_t of the launch.
 hipError_t launch_init(ModelId m, Prec p, const KParams& kp, const double* rho, const double* U,
                        const double* T, void* f, hipStream_t s);
-hipError_t launch_fix_planes(ModelId m, Prec p, const KParams& kp, void* f, long long plane,
-                             int n_lo, int n_hi, int nlast, const FixedState& lo,
-                             const FixedState& hi, hipStream_t s);
 hipError_t launch_set_pop(ModelId m, Prec p, const KParams& kp, const double* fin, void* f,
                           hipStream_t s);
 hipError_t launch_get_pop(ModelId m, Prec p, const KParams& kp, const void* f, double* fout,

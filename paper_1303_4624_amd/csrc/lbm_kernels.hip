@@ -429,6 +429,44 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accu
 }
 
 // ---------------------------------------------------------------------------
+// f^eq(r, U, T) of one cell in storage form, computed in float64 and
+// rounded once (Formula (3)); emit(I, value) receives population I::value in
+// increasing order.
+template <class M, class P, class Emit>
+__device__ __forceinline__ void feq_cell(const KParams& k, double r, double ux, double uy,
+                                         double uz, double T, Emit&& emit) {
+    using S = typename P::S;
+    const double d = T * k.invT0 - 1.0;
+    const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
+    const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
+    static_for<M::G>([&](auto GI) {
+        constexpr int g = decltype(GI)::value;
+        const GCoef gc = group_coef(k, g, u2, d);
+        const double w = k.W[g];
+        static_for<M::table.gsize[g]>([&](auto JI) {
+            constexpr int i = M::table.gstart[g] + decltype(JI)::value;
+            constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+            const double h = horner_h(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
+            if constexpr (P::shifted)
+                emit(std::integral_constant<int, i>{}, S(w * (r - k.rho0) + w * r * h));
+            else
+                emit(std::integral_constant<int, i>{}, S(w * r * (1.0 + h)));
+        });
+    });
+}
+
+// Store f^eq(r, U, T) of cell c in storage form FORM.
+template <class M, class P, int FORM>
+__device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const KParams& k,
+                                          long long c, double r, double ux, double uy,
+                                          double uz, double T) {
+    const PopAt<M, FORM> pa(k, c);
+    feq_cell<M, P>(k, r, ux, uy, uz, T, [&](auto I, typename P::S val) {
+        f[pa.template at<decltype(I)::value>()] = val;
+    });
+}
+
+// ---------------------------------------------------------------------------
 // Moments, equilibrium and BGK relaxation of one cell's incoming values v;
 // emit(I, value) receives post-collision population I::value, in increasing
 // order.  Returns the cell's macroscopic values.
@@ -490,13 +528,29 @@ __device__ __forceinline__ Macro relax_cell(const KParams& k, const typename P::
 //             out = omc v + omega_eff W rho (1 + h)    (F64)
 // with omc + omega_eff = 1 exactly, so mass, momentum and energy are
 // conserved up to the rounding of each cell's own values.
-template <class M, class P, bool STORE_MOM>
+//
+// HOLD: rows inside the held planes of the slowest axis (the fixed end
+// planes of the shock tube) store f^eq of the held state instead; the test
+// is uniform over a block.
+template <class M, class P, bool STORE_MOM, bool HOLD>
 __global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
 void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst, KParams k,
             typename P::S* __restrict__ mom) {
     using S = typename P::S;
     constexpr int D = M::D;
     const Cell cl = row_cell(k);
+
+    if constexpr (HOLD) {
+        const int sl = (D == 3) ? cl.z : cl.y;
+        const int L = (D == 3) ? k.nz : k.ny;
+        if (sl < k.hold_lo || sl >= L - k.hold_hi) {
+            const FixedState& st = (sl < k.hold_lo) ? k.hold[0] : k.hold[1];
+            PlaneWriter<S> out_w(dst, k, cl, M::Q);
+            feq_cell<M, P>(k, st.rho, st.U[0], st.U[1], st.U[2], st.T,
+                           [&](auto, S val) { out_w.put(val); });
+            return;
+        }
+    }
 
     S v[M::Q];
     gather<M, +1>(src, k, cl, v);
@@ -555,32 +609,6 @@ void k_step_aa(typename P::S* f, KParams k) {
 }
 
 // ---------------------------------------------------------------------------
-// Store f^eq(r, U, T) of one cell, computed in float64 (Formula (3)).
-template <class M, class P, int FORM>
-__device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const KParams& k,
-                                          long long c, double r, double ux, double uy,
-                                          double uz, double T) {
-    const double d = T * k.invT0 - 1.0;
-    const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
-    const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
-    const PopAt<M, FORM> pa(k, c);
-    static_for<M::G>([&](auto GI) {
-        constexpr int g = decltype(GI)::value;
-        const GCoef gc = group_coef(k, g, u2, d);
-        const double w = k.W[g];
-        static_for<M::table.gsize[g]>([&](auto JI) {
-            constexpr int i = M::table.gstart[g] + decltype(JI)::value;
-            constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-            const double h = horner_h(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
-            if constexpr (P::shifted) {
-                f[pa.template at<i>()] = static_cast<float>(w * (r - k.rho0) + w * r * h);
-            } else {
-                f[pa.template at<i>()] = w * r * (1.0 + h);
-            }
-        });
-    });
-}
-
 // f = f^eq(rho, U, T) from float64 fields.
 template <class M, class P, int FORM>
 __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ rho,
@@ -591,23 +619,6 @@ __global__ __launch_bounds__(kBlock) void k_init(const double* __restrict__ rho,
     if (c >= k.N) return;
     store_feq<M, P, FORM>(f, k, c, rho[c], U[c], U[k.N + c], (M::D == 3) ? U[2 * k.N + c] : 0.0,
                           T[c]);
-}
-
-// Hold the first n_lo and the last n_hi planes of the slowest axis at the
-// equilibrium of fixed states: f* = f^eq(lo) resp. f^eq(hi) there.  One
-// thread per cell of those planes; `plane` = cells per plane, `nlast` =
-// planes along the slowest axis.
-template <class M, class P>
-__global__ __launch_bounds__(kBlock) void k_fix_planes(typename P::S* __restrict__ f, KParams k,
-                                                       long long plane, int n_lo, int n_hi,
-                                                       int nlast, FixedState lo, FixedState hi) {
-    const long long t = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const long long cells_lo = plane * n_lo;
-    if (t >= plane * (n_lo + n_hi)) return;
-    const bool is_lo = t < cells_lo;
-    const long long c = is_lo ? t : static_cast<long long>(nlast - n_hi) * plane + (t - cells_lo);
-    const FixedState& st = is_lo ? lo : hi;
-    store_feq<M, P, kFormAB>(f, k, c, st.rho, st.U[0], st.U[1], st.U[2], st.T);
 }
 
 // Copy float64 f[Q][N] into storage, and back.
@@ -1004,20 +1015,6 @@ hipError_t launch_init(ModelId m, Prec p, const KParams& kp, const double* rho, 
     });
 }
 
-hipError_t launch_fix_planes(ModelId m, Prec p, const KParams& kp, void* f, long long plane,
-                             int n_lo, int n_hi, int nlast, const FixedState& lo,
-                             const FixedState& hi, hipStream_t s) {
-    const long long cells = plane * (n_lo + n_hi);
-    if (cells <= 0) return hipSuccess;
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        hipLaunchKernelGGL((k_fix_planes<M, P>), dim3(cell_blocks(cells)), dim3(kBlock), 0, s,
-                           static_cast<typename P::S*>(f), kp, plane, n_lo, n_hi, nlast, lo, hi);
-        return hipGetLastError();
-    });
-}
-
 hipError_t launch_set_pop(ModelId m, Prec p, const KParams& kp, const double* fin, void* f,
                           hipStream_t s) {
     return with_types(m, p, [&](auto M_, auto P_) {
@@ -1051,14 +1048,19 @@ hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, vo
         using M = decltype(M_);
         using P = decltype(P_);
         using S = typename P::S;
+        const dim3 grid(static_cast<unsigned>(blocks));
         if (mom_out) {
-            hipLaunchKernelGGL((k_step<M, P, true>), dim3(static_cast<unsigned>(blocks)),
-                               dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<const S*>(src), static_cast<S*>(dst),
-                               kp, static_cast<S*>(mom_out));
+            hipLaunchKernelGGL((k_step<M, P, true, false>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
+                               static_cast<const S*>(src), static_cast<S*>(dst), kp,
+                               static_cast<S*>(mom_out));
+        } else if (kp.hold_lo + kp.hold_hi > 0) {
+            hipLaunchKernelGGL((k_step<M, P, false, true>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
+                               static_cast<const S*>(src), static_cast<S*>(dst), kp,
+                               static_cast<S*>(nullptr));
         } else {
-            hipLaunchKernelGGL((k_step<M, P, false>), dim3(static_cast<unsigned>(blocks)),
-                               dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<const S*>(src), static_cast<S*>(dst),
-                               kp, static_cast<S*>(nullptr));
+            hipLaunchKernelGGL((k_step<M, P, false, false>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
+                               static_cast<const S*>(src), static_cast<S*>(dst), kp,
+                               static_cast<S*>(nullptr));
         }
         return hipGetLastError();
     });
