@@ -39,7 +39,10 @@ def _loss_gpu(sim, rho, U, T, n, tgt):
 
 
 @pytest.mark.parametrize("model,extent,n,k", [("D3Q95", (20, 10, 8), 10, 3),
-                                              ("D2Q33", (20, 12), 40, 9)])
+                                              ("D2Q33", (20, 12), 40, 9),
+                                              # two single-step segments; ragged tiny grids
+                                              ("D3Q95", (7, 5, 4), 2, 1),
+                                              ("D2Q33", (9, 6), 3, 2)])
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32s", 1e-3)])
 def test_adjoint_matches_oracle_autograd(model, extent, n, k, precision, tol):
     # dL/domega = (sum_t A^t - (n-1) K) / (1 - omega) cancels: its rounding
