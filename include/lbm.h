@@ -31,7 +31,8 @@
  *    rows are contiguous and population-major inside the group, the g rows
  *    of one population adjacent (g = 2 in 3D when ny is even, else 1):
  *    population i of cell (x, y, z) is element
- *    ((z*ny/g + y/g)*Q*g + i*g + y%g)*nx + x (two-buffer streaming; with
+ *    ((z*ny/g + y/g)*Q*g + i*g + y%g)*rs + x, with the run stride rs = nx
+ *    rounded up to a multiple of 32 when nx >= 32 (two-buffer streaming; with
  *    LBM_STREAM_AA the slot of a value alternates, see lbm_set_streaming).
  *    The layout is internal to the library (sizes from
  *    lbm_workspace_bytes).  In

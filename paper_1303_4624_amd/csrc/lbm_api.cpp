@@ -68,7 +68,11 @@ int fail_hip(lbm_ctx* ctx, hipError_t e, const char* what) {
 size_t elem_bytes(Prec p) { return p == Prec::F64 ? 8 : 4; }
 
 // Elements between two population runs of a grid row.
-long long run_stride(const lbm_ctx* ctx) { return ctx->extent[0] + lbm::kRunPad; }
+long long run_stride_of(long long nx) {
+    const long long a = nx < lbm::kRunAlign ? 1 : lbm::kRunAlign;
+    return (nx + a - 1) / a * a + lbm::kRunPad;
+}
+long long run_stride(const lbm_ctx* ctx) { return run_stride_of(ctx->extent[0]); }
 
 size_t pop_bytes(const lbm_ctx* ctx) {
     return static_cast<size_t>(ctx->N / ctx->extent[0]) * run_stride(ctx) * ctx->Q *
@@ -301,7 +305,7 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
         return fail(nullptr, LBM_E_INVALID, "grid too large for one launch");
     // The kernels address one slab of the slowest axis (all populations of a
     // z-plane in 3D, of a row in 2D) with 32-bit byte offsets.
-    const long long slab = (extent[0] + lbm::kRunPad) * (D == 3 ? extent[1] : 1) * Q *
+    const long long slab = run_stride_of(extent[0]) * (D == 3 ? extent[1] : 1) * Q *
                            (precision == LBM_FP64 ? 8LL : 4LL);
     if (slab >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID,

@@ -23,6 +23,15 @@ namespace lbm {
 #endif
 constexpr int kRunPad = LBM_RUN_PAD;
 
+// Rows of at least this many cells get a run stride rounded up to a multiple
+// of it (32 elements: every population run starts on a 128-byte line).
+// Measured on D3Q95 FP32-shifted: +8 % to +20 % for 376^3, 392^3, 400^3;
+// no change where nx is already a multiple.
+#ifndef LBM_RUN_ALIGN
+#define LBM_RUN_ALIGN 32
+#endif
+constexpr int kRunAlign = LBM_RUN_ALIGN;
+
 // Rows (consecutive y, same z) whose population runs are interleaved in 3D
 // (a power of two),
 // when ny is a multiple of it (else 1); 2D rows are long enough alone.
