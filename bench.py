@@ -149,8 +149,9 @@ def run_aa(extent, steps, tile=None):
             "ic": "smooth" if tile is None else f"smooth {tile[0]}^3 tile repeated"}
 
 
-def run_tube(wname, precision):
-    """The shock tube with held end planes: time its whole run."""
+def run_tube(wname, precision, graph_steps=0):
+    """The shock tube with held end planes: time its whole run (optionally
+    replayed in HIP graphs of graph_steps steps, on a side stream)."""
     import torch
     from paper_1303_4624_amd import Simulation
     from synth_inputs import WORKLOADS, tube_states, workload_ic
@@ -158,17 +159,27 @@ def run_tube(wname, precision):
     D = len(w.extent)
     (lr, lt), (rr, rt) = tube_states(w)
     rho, U, th = workload_ic(w)
-    sim = Simulation(w.model, w.extent, w.omega, precision=precision)
-    sim.init_fields(rho, U, th * sim.T0)
-    nh = int(w.extra["hold"])
-    sim.set_fixed_planes(nh, nh, (lr,) + (0.0,) * D + (lt * sim.T0,),
-                         (rr,) + (0.0,) * D + (rt * sim.T0,))
-    wall, ev = timed_steps(sim, w.steps, 0)
-    N = sim.N
-    sim.close()
+    stream = torch.cuda.Stream() if graph_steps else torch.cuda.current_stream()
+    with torch.cuda.stream(stream):
+        sim = Simulation(w.model, w.extent, w.omega, precision=precision, stream=stream)
+        sim.init_fields(rho, U, th * sim.T0)
+        nh = int(w.extra["hold"])
+        sim.set_fixed_planes(nh, nh, (lr,) + (0.0,) * D + (lt * sim.T0,),
+                             (rr,) + (0.0,) * D + (rt * sim.T0,))
+        if graph_steps:
+            sim.set_graph_steps(graph_steps)
+            sim.step(graph_steps)              # capture outside the timed region
+            sim.init_fields(rho, U, th * sim.T0)
+        wall, ev = timed_steps(sim, w.steps, 0)
+        N = sim.N
+        sim.close()
+    torch.cuda.synchronize()
     torch.cuda.empty_cache()
-    return {"steps": w.steps, "ms_per_step": round(ev / w.steps * 1e3, 4),
-            "mlups": round(N * w.steps / ev / 1e6, 2)}
+    out = {"steps": w.steps, "ms_per_step": round(ev / w.steps * 1e3, 4),
+           "mlups": round(N * w.steps / ev / 1e6, 2)}
+    if graph_steps:
+        out["graph_steps"] = graph_steps
+    return out
 
 
 def run_fwd_adjoint(extent, omega, n, k, keep=1):
@@ -381,6 +392,7 @@ def main():
         for wname in ("d3q95_11x11x800_tube", "d2q33_11x800_tube"):
             for prec in ("fp64", "fp32s"):
                 out[f"{wname}_{prec}"] = run_tube(wname, prec)
+                out[f"{wname}_{prec}_graph"] = run_tube(wname, prec, graph_steps=40)
         log("[bench] forward + adjoint on 128^3")
         # 128^3 fits many times over in HBM: keep the moments of every segment
         # (no recomputation); the minimum-memory variant keeps one segment.

@@ -288,6 +288,20 @@ int lbm_conservation(lbm_ctx* ctx, double* out);
 int lbm_set_fixed_planes(lbm_ctx* ctx, int n_lo, int n_hi, const double* state_lo,
                          const double* state_hi);
 
+/*
+ * lbm_set_graph_steps - replay lbm_step in HIP graphs of `steps` update steps
+ * (the update rule, unchanged): the first call that needs them captures the
+ * launches of `steps` steps once, later calls replay the graph for every full
+ * block of `steps` steps and launch the remainder one by one.  Launch-bound
+ * small grids (the shock tube) gain; the arithmetic and results are the same
+ * bit for bit.  steps must be even (the buffers and storage form return to
+ * their state after an even count), 0 turns replay off (the default).  The
+ * graph is rebuilt after lbm_bind, lbm_set_omega or lbm_set_fixed_planes.
+ * Needs a non-null stream (LBM_E_UNSUPPORTED otherwise); LBM_E_INVALID for
+ * odd or negative steps.  Graphs hold no memset nodes.
+ */
+int lbm_set_graph_steps(lbm_ctx* ctx, int steps);
+
 /* lbm_set_omega - change the relaxation frequency (0 <= omega < 2). */
 int lbm_set_omega(lbm_ctx* ctx, double omega);
 

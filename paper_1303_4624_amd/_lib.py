@@ -32,7 +32,8 @@ LBM_MAX_Q = 95
 EXPORTED = [
     "lbm_velocity_set", "lbm_equation_count", "lbm_model_build", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments",
-    "lbm_conservation", "lbm_set_fixed_planes", "lbm_set_streaming", "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
+    "lbm_conservation", "lbm_set_fixed_planes", "lbm_set_streaming", "lbm_set_graph_steps",
+    "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_str",
     "lbm_last_error",
 ]
@@ -70,6 +71,7 @@ _SIGS = {
     "lbm_conservation": (_c.c_int, [_vp, _pd]),
     "lbm_set_fixed_planes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _pd, _pd]),
     "lbm_set_streaming": (_c.c_int, [_vp, _c.c_int]),
+    "lbm_set_graph_steps": (_c.c_int, [_vp, _c.c_int]),
     "lbm_set_omega": (_c.c_int, [_vp, _c.c_double]),
     "lbm_checkpoint_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _psz]),
     "lbm_run_checkpointed": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _vp, _sz]),
@@ -230,6 +232,10 @@ def lbm_set_fixed_planes(ctx, n_lo: int, n_hi: int, state_lo=None, state_hi=None
 
 def lbm_set_streaming(ctx, scheme: int) -> None:
     _check(library().lbm_set_streaming(ctx, int(scheme)), "lbm_set_streaming", ctx)
+
+
+def lbm_set_graph_steps(ctx, steps: int) -> None:
+    _check(library().lbm_set_graph_steps(ctx, int(steps)), "lbm_set_graph_steps", ctx)
 
 
 def lbm_set_omega(ctx, omega: float) -> None:

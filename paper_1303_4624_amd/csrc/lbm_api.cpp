@@ -40,6 +40,11 @@ struct lbm_ctx {
     bool initialized = false;
     KParams kp{};
     bool aa = false;                // one buffer, in-place AA-pattern steps
+    // Graph replay of lbm_step: G steps captured once and replayed while the
+    // launch state (buffer parity, storage form) matches the captured one.
+    int graph_steps = 0;
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_cur = -1, graph_form = -1;
     int hold_lo = 0, hold_hi = 0;   // planes held at f^eq at each end of the slowest axis
     lbm::FixedState hold[2]{};
     std::string err;
@@ -344,6 +349,60 @@ LBM_API int lbm_workspace_bytes(const lbm_ctx* ctx, size_t* pop, size_t* scratch
     return LBM_OK;
 }
 
+namespace {
+
+void drop_graph(lbm_ctx* ctx) {
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    ctx->graph_exec = nullptr;
+    ctx->graph_cur = ctx->graph_form = -1;
+}
+
+// One update step on the context's stream (two-buffer or in place).
+hipError_t launch_one_step(lbm_ctx* ctx) {
+    if (ctx->aa) {
+        const bool push = ctx->kp.form == lbm::kFormSwapped;
+        hipError_t e =
+            lbm::launch_step_aa(ctx->model, ctx->prec, ctx->kp, ctx->f[0], push, ctx->stream);
+        if (e == hipSuccess) ctx->kp.form = push ? lbm::kFormPushed : lbm::kFormSwapped;
+        return e;
+    }
+    hipError_t e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
+                                    ctx->f[1 - ctx->cur], nullptr, ctx->stream);
+    if (e == hipSuccess) ctx->cur = 1 - ctx->cur;
+    return e;
+}
+
+// Captures graph_steps steps from the current launch state.  The state
+// after an even number of steps equals the one before, so the graph can be
+// replayed as long as that state is current.
+int capture_graph(lbm_ctx* ctx) {
+    drop_graph(ctx);
+    const int cur0 = ctx->cur, form0 = ctx->kp.form;
+    hipError_t e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int t = 0; t < ctx->graph_steps && le == hipSuccess; ++t) le = launch_one_step(ctx);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(ctx->stream, &g);
+    ctx->cur = cur0;
+    ctx->kp.form = form0;
+    if (le != hipSuccess || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail_hip(ctx, le != hipSuccess ? le : e, "graph capture of the step");
+    }
+    e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+        ctx->graph_exec = nullptr;
+        return fail_hip(ctx, e, "hipGraphInstantiate");
+    }
+    ctx->graph_cur = cur0;
+    ctx->graph_form = form0;
+    return LBM_OK;
+}
+
+}  // namespace
+
 LBM_API int lbm_bind(lbm_ctx* ctx, void* f_a, void* f_b, void* scratch) {
     if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
     int dev = -1;
@@ -375,6 +434,7 @@ LBM_API int lbm_bind(lbm_ctx* ctx, void* f_a, void* f_b, void* scratch) {
     ctx->bound = true;
     ctx->initialized = false;
     ctx->kp.form = initial_form(ctx);
+    drop_graph(ctx);
     ctx->err.clear();
     return LBM_OK;
 }
@@ -431,22 +491,33 @@ LBM_API int lbm_step(lbm_ctx* ctx, int n) {
     if ((rc = require_init(ctx)) != LBM_OK) return rc;
     if (n < 0) return fail(ctx, LBM_E_INVALID, "n must be >= 0");
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
-    if (ctx->aa) {
-        for (int t = 0; t < n; ++t) {
-            const bool push = ctx->kp.form == lbm::kFormSwapped;
-            hipError_t e =
-                lbm::launch_step_aa(ctx->model, ctx->prec, ctx->kp, ctx->f[0], push, ctx->stream);
-            if (e != hipSuccess) return fail_hip(ctx, e, "in-place step kernel");
-            ctx->kp.form = push ? lbm::kFormPushed : lbm::kFormSwapped;
+    int left = n;
+    if (ctx->graph_steps > 0) {
+        while (left >= ctx->graph_steps) {
+            if (!ctx->graph_exec || ctx->graph_cur != ctx->cur ||
+                ctx->graph_form != ctx->kp.form) {
+                if ((rc = capture_graph(ctx)) != LBM_OK) return rc;
+            }
+            hipError_t e = hipGraphLaunch(ctx->graph_exec, ctx->stream);
+            if (e != hipSuccess) return fail_hip(ctx, e, "hipGraphLaunch");
+            left -= ctx->graph_steps;
         }
-        return LBM_OK;
     }
-    for (int t = 0; t < n; ++t) {
-        hipError_t e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
-                                        ctx->f[1 - ctx->cur], nullptr, ctx->stream);
-        if (e != hipSuccess) return fail_hip(ctx, e, "step kernel");
-        ctx->cur = 1 - ctx->cur;
+    for (; left > 0; --left) {
+        hipError_t e = launch_one_step(ctx);
+        if (e != hipSuccess) return fail_hip(ctx, e, ctx->aa ? "in-place step kernel" : "step kernel");
     }
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_graph_steps(lbm_ctx* ctx, int steps) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (steps < 0 || steps % 2 != 0)
+        return fail(ctx, LBM_E_INVALID, "steps must be an even number >= 0");
+    if (steps > 0 && !ctx->stream)
+        return fail(ctx, LBM_E_UNSUPPORTED, "graph replay needs a stream other than the null stream");
+    drop_graph(ctx);
+    ctx->graph_steps = steps;
     return LBM_OK;
 }
 
@@ -481,6 +552,7 @@ LBM_API int lbm_set_fixed_planes(lbm_ctx* ctx, int n_lo, int n_hi, const double*
     ctx->kp.hold_hi = n_hi;
     ctx->kp.hold[0] = fs[0];
     ctx->kp.hold[1] = fs[1];
+    drop_graph(ctx);
     return LBM_OK;
 }
 
@@ -560,6 +632,7 @@ LBM_API int lbm_set_omega(lbm_ctx* ctx, double omega) {
     if (!omega_ok(omega)) return fail(ctx, LBM_E_INVALID, "omega must be in [0, 2)");
     ctx->omega = omega;
     fill_kparams(ctx);
+    drop_graph(ctx);
     return LBM_OK;
 }
 
@@ -800,6 +873,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
 }
 
 LBM_API int lbm_destroy(lbm_ctx* ctx) {
+    if (ctx) drop_graph(ctx);
     delete ctx;
     return LBM_OK;
 }

@@ -116,6 +116,11 @@ class Simulation:
                 raise ValueError(f"a held state needs D + 2 = {self.D + 2} values")
         L.lbm_set_fixed_planes(self.ctx, n_lo, n_hi, state_lo, state_hi)
 
+    def set_graph_steps(self, steps: int) -> None:
+        """Replay step() in HIP graphs of `steps` (even) steps; 0 turns it off.
+        Needs a non-default stream (pass ``stream=torch.cuda.Stream()``)."""
+        L.lbm_set_graph_steps(self.ctx, steps)
+
     def set_omega(self, omega: float) -> None:
         L.lbm_set_omega(self.ctx, omega)
         self.omega = float(omega)

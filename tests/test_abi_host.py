@@ -222,3 +222,15 @@ def test_missing_library_fails_loudly(tmp_path):
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True,
                          timeout=120, cwd=ROOT)
     assert "raised:" in res.stdout and "no CPU fallback" in res.stdout, res.stdout + res.stderr
+
+
+def test_graph_steps_validation():
+    ctx = L.lbm_create(**_args("D3Q95", extent=[6, 4, 20]))    # null stream
+    try:
+        L.lbm_set_graph_steps(ctx, 0)
+        for steps, want in [(3, L.LBM_E_INVALID), (-2, L.LBM_E_INVALID), (4, L.LBM_E_UNSUPPORTED)]:
+            with pytest.raises(L.LBMError) as ex:
+                L.lbm_set_graph_steps(ctx, steps)
+            assert ex.value.status == want, steps
+    finally:
+        L.lbm_destroy(ctx)
