@@ -91,37 +91,43 @@ def run_headline(extent, omega, steps, warmup):
     return wall, ev, ok, cons
 
 
-def run_fp64_and_error(extent, omega, steps_time, steps_err, model="D3Q95"):
+def run_fp64_and_error(extent, omega, steps_time, steps_err, model="D3Q95", steps_err_long=0):
     """FP64 and FP32-shifted throughput on `extent`, and the FP32-shifted vs
-    FP64 GPU error after `steps_err` steps from the same initial fields."""
+    FP64 GPU error after `steps_err` (and `steps_err_long`) steps from the
+    same initial fields."""
     import torch
     from paper_1303_4624_amd import Simulation
     from synth_inputs import smooth_ic
     rho, U, th = smooth_ic(extent)
     out = {}
     fields = {}
+    marks = [m for m in (steps_err, steps_err_long) if m]
     for prec in ("fp64", "fp32s"):
         sim = Simulation(model, extent, omega, precision=prec)
         sim.init_fields(rho, U, th * sim.T0)
-        sim.step(steps_err)
-        fields[prec] = [x.clone() for x in sim.moments()]
+        done = 0
+        for m in marks:
+            sim.step(m - done)
+            done = m
+            fields[(prec, m)] = [x.clone() for x in sim.moments()]
         T0 = sim.T0
         wall, ev = timed_steps(sim, steps_time, 2)
         out[prec] = {"mlups": sim.N * steps_time / ev / 1e6, "ms_per_step": ev / steps_time * 1e3}
         sim.close()
         del sim
         torch.cuda.empty_cache()
-    r64, u64, t64 = fields["fp64"]
-    r32, u32, t32 = fields["fp32s"]
-    err = {
-        "rho": float((r32 - r64).abs().max() / r64.abs().max()),
-        "U": float((u32 - u64).abs().max() / u64.abs().max()),
-        "T": float((t32 - t64).abs().max() / T0),
-        "steps": steps_err,
-    }
+
+    def err(m):
+        r64, u64, t64 = fields[("fp64", m)]
+        r32, u32, t32 = fields[("fp32s", m)]
+        return {"rho": float((r32 - r64).abs().max() / r64.abs().max()),
+                "U": float((u32 - u64).abs().max() / u64.abs().max()),
+                "T": float((t32 - t64).abs().max() / T0), "steps": m}
+
+    errs = [err(m) for m in marks]
     del fields
     torch.cuda.empty_cache()
-    return out, err
+    return out, (errs[0] if len(errs) == 1 else errs)
 
 
 def run_aa(extent, steps, tile=None):
@@ -372,7 +378,9 @@ def main():
         out["roofline"]["copy_GBs"] = round(cbw, 1)
         out["roofline"]["frac_of_copy"] = round(achieved / cbw, 4)
         log("[bench] fp64 vs fp32s on 256^3")
-        thr, err = run_fp64_and_error((256, 256, 256), 1.5, 100, 200)
+        thr, errs = run_fp64_and_error((256, 256, 256), 1.5, 100, 200, steps_err_long=1000)
+        err = errs[0]
+        out["fp32s_vs_fp64_256c_1000_steps"] = errs[1]
         out["fp64_256c"] = {k: round(v, 3) for k, v in thr["fp64"].items()}
         out["fp32s_256c"] = {k: round(v, 3) for k, v in thr["fp32s"].items()}
         out["fp64_256c"]["roofline_frac"] = round(
