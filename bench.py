@@ -155,6 +155,10 @@ def run_aa(extent, steps, tile=None):
             "ic": "smooth" if tile is None else f"smooth {tile[0]}^3 tile repeated"}
 
 
+TUBE_PLATEAUS = {"d3q95_11x11x800_tube": ((300, 480), (540, 700)),
+                 "d2q33_11x800_tube": ((340, 390), (470, 580))}
+
+
 def run_tube(wname, precision, graph_steps=0):
     """The shock tube with held end planes: time its whole run (optionally
     replayed in HIP graphs of graph_steps steps, on a side stream)."""
@@ -178,11 +182,22 @@ def run_tube(wname, precision, graph_steps=0):
             sim.init_fields(rho, U, th * sim.T0)
         wall, ev = timed_steps(sim, w.steps, 0)
         N = sim.N
+        r, _, T = sim.moments()
+        axes = tuple(range(1, D))
+        rz = r.mean(dim=axes).cpu().numpy()
+        tz = (T.mean(dim=axes) / sim.T0).cpu().numpy()
         sim.close()
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+    # plateau means between the rarefaction tail, the contact and the shock
+    # at t = 120 (the experiment's comparison quantity)
+    (a, b), (c, d) = TUBE_PLATEAUS[wname]
     out = {"steps": w.steps, "ms_per_step": round(ev / w.steps * 1e3, 4),
-           "mlups": round(N * w.steps / ev / 1e6, 2)}
+           "mlups": round(N * w.steps / ev / 1e6, 2),
+           "plateaus": {"rho_left": round(float(rz[a:b].mean()), 5),
+                        "rho_right": round(float(rz[c:d].mean()), 5),
+                        "theta_left": round(float(tz[a:b].mean()), 5),
+                        "theta_right": round(float(tz[c:d].mean()), 5)}}
     if graph_steps:
         out["graph_steps"] = graph_steps
     return out
