@@ -319,8 +319,9 @@ int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, int keep, size_t* byt
  * lbm_run_checkpointed - like lbm_step(n), and fills ckpt for lbm_adjoint:
  * the stored state at t = 0, k, 2k, ... (before the step that starts each
  * segment) in slot s = t/k, the final state in slot ceil(n/k), and after the
- * slots the moments of every step of the last `keep` segments.  Snapshots
- * after the first are written in place by the step that produces them.
+ * slots the moments of every step of the last `keep` segments.  Snapshot 0
+ * is a copy of the bound state; later snapshots are written in place by the
+ * step that produces them.
  * n >= 1, k >= 1, keep >= 1.
  */
 int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckpt, size_t ckpt_bytes);
@@ -329,7 +330,7 @@ int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckpt, size_
  * lbm_adjoint_workspace_bytes - size of the workspace lbm_adjoint needs for
  * the same (n, k, keep): three population-sized buffers (adjoint ping-pong
  * and recomputation), k steps of stored moments when some segment is
- * recomputed, and the float64 reduction partials.
+ * recomputed, the float64 reduction partials and one float64 per segment.
  */
 int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int n, int k, int keep, size_t* bytes);
 
@@ -348,10 +349,13 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int n, int k, int keep, size
  *   mu_i = nu^{t+1}_i(x + e_i),  G_m = sum_k mu_k d f_k^eq / d m at m^t,
  * with m = (rho, rho U, sum f |e|^2), for t = n-1 .. 1, from
  * nu^n_i(x) = dL/drho_n(x); dL/df*^0 is the transposed streaming of nu^1.
- * Because the update is homogeneous of degree one in f, <dL/df*^t, f*^t> is
- * the same constant K = sum_x dL/drho_n rho_n for every t, so
- *   dL/domega = sum_{t=1}^{n-1} (sum_x sum_i mu_i f_i^eq(m^t) - K) / (1 - omega)
- * needs only the stored moments; it is reduced in float64.
+ * Because the update is homogeneous of degree one in f, K(t) = <nu^t, S f*^{t-1}>
+ * is the same for every t (K(n) = sum_x dL/drho_n rho_n), so
+ *   dL/domega = sum_{t=1}^{n-1} (sum_x sum_i mu_i f_i^eq(m^t) - K(t+1)) / (1 - omega)
+ * needs only the stored moments; it is reduced in float64.  The adjoint
+ * state is stored (and rounded) in the storage precision, which makes K
+ * drift slowly; K is therefore measured at t = s k + 1 against each snapshot
+ * and at t = n, and K(t) is taken linearly between those points.
  *
  *   ckpt, ckpt_bytes   : the checkpoints of the forward run.
  *   rho_init, U_init, T_init : device float64 initial fields of that run.

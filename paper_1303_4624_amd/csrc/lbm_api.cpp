@@ -688,14 +688,12 @@ LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckp
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
     const size_t pb = pop_bytes(ctx);
     char* ck = static_cast<char*>(ckpt);
-    // Snapshot 0 is a copy (needed only if segment 0 is recomputed); every
-    // later snapshot is written directly by the step that ends the previous
-    // segment, and the next step reads it there.
-    hipError_t e = hipSuccess;
-    if (c.t_keep > 0) {
-        e = hipMemcpyAsync(ck, ctx->f[ctx->cur], pb, hipMemcpyDeviceToDevice, ctx->stream);
-        if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
-    }
+    // Snapshot 0 is a copy (the adjoint recomputes segment 0 from it, or
+    // measures its invariant there); every later snapshot is written directly
+    // by the step that ends the previous segment, and the next step reads it
+    // there.
+    hipError_t e = hipMemcpyAsync(ck, ctx->f[ctx->cur], pb, hipMemcpyDeviceToDevice, ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy");
     const void* src = ctx->f[ctx->cur];
     for (int t = 0; t < n; ++t) {
         const bool to_slot = ((t + 1) % k == 0) && (t + 1 < n);
@@ -715,14 +713,17 @@ LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckp
 
 namespace {
 
+// Adjoint workspace: [three adjoint-state buffers][moments of one recomputed
+// segment][partials of A][partials of K(n)][partials of one invariant mark]
+// [A, K(n), one invariant mark per segment].
 struct AdjLayout {
     size_t pop;       // stride of one population-sized buffer
     size_t mom_step;  // bytes of one step of stored moments
-    size_t off_mom, off_partA, off_partK, off_out, total;
+    size_t off_mom, off_partA, off_partK, off_partM, off_out, total;
     long long nA, nK;
 };
 
-AdjLayout adj_layout(const lbm_ctx* ctx, int k, bool recompute) {
+AdjLayout adj_layout(const lbm_ctx* ctx, int k, int segs, bool recompute) {
     AdjLayout L;
     L.pop = round_up(pop_bytes(ctx));
     L.mom_step = round_up(static_cast<size_t>(ctx->N) * (ctx->D + 2) * elem_bytes(ctx->prec));
@@ -731,8 +732,9 @@ AdjLayout adj_layout(const lbm_ctx* ctx, int k, bool recompute) {
     L.nK = (ctx->N + 255) / 256;
     L.off_partA = L.off_mom + (recompute ? static_cast<size_t>(k) * L.mom_step : 0);
     L.off_partK = L.off_partA + round_up(static_cast<size_t>(L.nA) * 8);
-    L.off_out = L.off_partK + round_up(static_cast<size_t>(L.nK) * 8);
-    L.total = L.off_out + round_up(2 * 8);
+    L.off_partM = L.off_partK + round_up(static_cast<size_t>(L.nK) * 8);
+    L.off_out = L.off_partM + round_up(static_cast<size_t>(L.nA) * 8);
+    L.total = L.off_out + round_up(static_cast<size_t>(2 + segs) * 8);
     return L;
 }
 
@@ -743,7 +745,8 @@ LBM_API int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int n, int k, int ke
     if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
     if (n < 1 || k < 1 || keep < 1 || !bytes)
         return fail(nullptr, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
-    *bytes = adj_layout(ctx, k, ck_layout(ctx, n, k, keep).t_keep > 0).total;
+    const CkLayout C = ck_layout(ctx, n, k, keep);
+    *bytes = adj_layout(ctx, k, C.segs, C.t_keep > 0).total;
     return LBM_OK;
 }
 
@@ -767,7 +770,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
     const CkLayout C = ck_layout(ctx, n, k, keep);
     const size_t need_ck = C.total;
     if (ckpt_bytes < need_ck) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
-    const AdjLayout L = adj_layout(ctx, k, C.t_keep > 0);
+    const AdjLayout L = adj_layout(ctx, k, C.segs, C.t_keep > 0);
     if (ws_bytes < L.total) return fail(ctx, LBM_E_INVALID, "adjoint workspace too small");
     const size_t nb = static_cast<size_t>(ctx->N) * 8;
     if ((rc = check_dev(ctx, ckpt, need_ck, "ckpt")) != LBM_OK) return rc;
@@ -788,6 +791,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
     char* mom = ws + L.off_mom;
     double* partA = reinterpret_cast<double*>(ws + L.off_partA);
     double* partK = reinterpret_cast<double*>(ws + L.off_partK);
+    double* partM = reinterpret_cast<double*>(ws + L.off_partM);
     double* dout = reinterpret_cast<double*>(ws + L.off_out);
     const size_t ck_stride = C.stride;
     const char* ck = static_cast<const char*>(ckpt);
@@ -841,6 +845,13 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
             if (e != hipSuccess) return fail_hip(ctx, e, "adjoint step kernel");
             lam = nxt;
         }
+        if (dL_domega) {
+            // invariant mark K(t0 + 1) = <nu^{t0+1}, S B^{t0}>, B^{t0} the snapshot
+            e = lbm::launch_pair_dot(ctx->model, ctx->prec, ctx->kp, ck + s * ck_stride, B[lam],
+                                     partM, st);
+            if (e == hipSuccess) e = lbm::launch_sum_partials(partM, L.nA, 1, 1, dout + 2 + s, st);
+            if (e != hipSuccess) return fail_hip(ctx, e, "invariant kernel");
+        }
     }
     {
         // dL/dB^0 = S^T nu^1
@@ -859,13 +870,26 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
         e = lbm::launch_sum_partials(partA, L.nA, 1, 1, dout, st);
         if (e == hipSuccess) e = lbm::launch_sum_partials(partK, L.nK, 1, 1, dout + 1, st);
         if (e != hipSuccess) return fail_hip(ctx, e, "reduction kernel");
-        double h[2] = {0, 0};
-        e = hipMemcpyAsync(h, dout, sizeof(h), hipMemcpyDeviceToHost, st);
+        std::vector<double> h(2 + segs, 0.0);
+        e = hipMemcpyAsync(h.data(), dout, h.size() * sizeof(double), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return fail_hip(ctx, e, "copy of the omega gradient");
-        // A^t = <lambda_B^t, f^eq(m^t)> for t = 1 .. n-1; the t = n term is
-        // <lambda_B^n, f^eq(m^n)> - K = 0.
-        *dL_domega = (h[0] - static_cast<double>(n - 1) * h[1]) / (1.0 - ctx->omega);
+        // dL/domega = sum_{t=1}^{n-1} (A^t - K(t+1)) / (1 - omega) with
+        // A^t = <S^T nu^{t+1}, f^eq(m^t)> and K(tau) = <nu^tau, f^tau>.  K is
+        // the same at every tau in exact arithmetic; the stored adjoint state
+        // is rounded at every step, so K is measured at tau = s k + 1 (one
+        // mark per segment) and at tau = n, and summed as the piecewise linear
+        // interpolant through those marks.
+        double sum_k = 0.0;
+        for (int s = 0; s < segs; ++s) {
+            const long long a = static_cast<long long>(s) * k + 1;
+            const long long b = (s + 1 < segs) ? a + k : n;
+            const double ka = h[2 + s];
+            const double kb = (s + 1 < segs) ? h[2 + s + 1] : h[1];
+            const double d = static_cast<double>(b - a);
+            if (b > a) sum_k += d * ka + 0.5 * (kb - ka) * (d + 1.0);
+        }
+        *dL_domega = (h[0] - sum_k) / (1.0 - ctx->omega);
         if (!std::isfinite(*dL_domega))
             return fail(ctx, LBM_E_NONFINITE, "omega gradient is not finite");
     }

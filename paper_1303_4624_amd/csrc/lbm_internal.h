@@ -115,6 +115,10 @@ hipError_t launch_lambda_init(ModelId m, Prec p, const KParams& kp, const void* 
 // mom == nullptr: transposed streaming only (no collision, partA unused).
 hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void* lam_src,
                                void* lam_dst, const void* mom, double* partA, hipStream_t s);
+// Per-block partial sums of <nu, S state> (state: stored populations, nu: an
+// adjoint state in the same layout), one double per step block.
+hipError_t launch_pair_dot(ModelId m, Prec p, const KParams& kp, const void* state,
+                           const void* nu, double* part, hipStream_t s);
 hipError_t launch_dT_init(ModelId m, Prec p, const KParams& kp, const void* lam0,
                           const double* rho, const double* U, const double* T, double* dT,
                           hipStream_t s);

@@ -773,6 +773,29 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     block_sum<1>(acc, partK + blockIdx.x, false);
 }
 
+// <nu, S B> per cell, summed per block in float64: the adjoint state nu of
+// the pre-collision populations against the streamed stored state S B (the
+// invariant <nu^t, f^t> of the step's homogeneity, measured at checkpoints).
+template <class M, class P>
+__global__ __launch_bounds__(P::max_block) void k_pair_dot(const typename P::S* __restrict__ state,
+                                                           const typename P::S* __restrict__ nu,
+                                                           KParams k, double* __restrict__ part) {
+    using S = typename P::S;
+    const Cell cl = row_cell(k);
+    S v[M::Q];
+    gather<M, +1>(state, k, cl, v);
+    const SlabAddr<M, S, const char> ad(reinterpret_cast<const char*>(nu), k, cl);
+    double acc[1] = {0.0};
+    static_for<M::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        const double f = P::shifted ? static_cast<double>(v[i]) + k.W[M::table.group[i]] * k.rho0
+                                    : static_cast<double>(v[i]);
+        acc[0] += static_cast<double>(load_pop<S>(ad.template at<i, 0, 0, 0>())) * f;
+    });
+    if (!cl.active) acc[0] = 0.0;
+    block_sum<1>(acc, part + blockIdx.x, false);
+}
+
 // Derivative coefficients of P = 1 + h with respect to s, u2 and d, per group:
 //   P_s  = a1 + s (2 a2 + s (1/2 + s/6))
 //   P_u2 = b0 + s (-1/2 - s/4),          b0 = -1/2 + u2/4 + d (D + 2 - X)/4
@@ -1155,6 +1178,19 @@ hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void*
                                static_cast<S*>(lam_dst), static_cast<const S*>(nullptr), kp,
                                static_cast<double*>(nullptr));
         }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_pair_dot(ModelId m, Prec p, const KParams& kp, const void* state,
+                           const void* nu, double* part, hipStream_t s) {
+    const long long blocks = step_blocks(m, p, kp);
+    return with_types(m, p, [&](auto M_, auto P_) {
+        using M = decltype(M_);
+        using P = decltype(P_);
+        using S = typename P::S;
+        hipLaunchKernelGGL((k_pair_dot<M, P>), dim3(static_cast<unsigned>(blocks)), dim3(kp.bx), 0,
+                           s, static_cast<const S*>(state), static_cast<const S*>(nu), kp, part);
         return hipGetLastError();
     });
 }

@@ -43,11 +43,12 @@ def _loss_gpu(sim, rho, U, T, n, tgt):
                                               # two single-step segments; ragged tiny grids
                                               ("D3Q95", (7, 5, 4), 2, 1),
                                               ("D2Q33", (9, 6), 3, 2)])
-@pytest.mark.parametrize("precision,tol", [("fp64", 1e-9), ("fp32s", 1e-3)])
-def test_adjoint_matches_oracle_autograd(model, extent, n, k, precision, tol):
-    # dL/domega = (sum_t A^t - (n-1) K) / (1 - omega) cancels: its rounding
-    # error is ~eps * n * sum|A| / |1 - omega|, so the target is a physical
-    # mismatch (another temperature field), not noise, as in the 128^3 case.
+@pytest.mark.parametrize("precision,tol,tol_w", [("fp64", 1e-9, 1e-9), ("fp32s", 1e-5, 2e-4)])
+def test_adjoint_matches_oracle_autograd(model, extent, n, k, precision, tol, tol_w):
+    # dL/domega = sum_t (A^t - K(t+1)) / (1 - omega) cancels: with K taken as
+    # a constant its FP32-shifted error reached 4e-4 on these cases; measured
+    # at the checkpoints it is <= 5e-5.  The target is a physical mismatch
+    # (another temperature field), not noise, as in the 128^3 case.
     _say("case", model, extent, n, k, precision)
     v = ovs.velocity_set(model)
     omega = 1.4
@@ -65,7 +66,7 @@ def test_adjoint_matches_oracle_autograd(model, extent, n, k, precision, tol):
     ew = abs(gw - gw_o) / abs(gw_o)
     _say("loss", L_g, L_o, "dT err", eT, "domega err", ew, gw, gw_o)
     assert abs(L_g - L_o) <= (1e-12 if precision == "fp64" else 1e-5) * L_o
-    assert eT <= tol and ew <= tol
+    assert eT <= tol and ew <= tol_w
 
 
 @pytest.mark.parametrize("keep", [2, 99])
@@ -122,7 +123,7 @@ def test_adjoint_128cube_200_steps_fp32s_vs_central_differences():
     fdw = (lp - lm) / (2 * h)
     ew = abs(gw - fdw) / abs(fdw)
     _say("omega: adjoint", gw, "fd", fdw, "rel", ew)
-    assert worst <= 1e-3 and ew <= 1e-3
+    assert worst <= 1e-3 and ew <= 1e-4
 
 
 def test_fp64_adjoint_vs_central_differences_ragged_segments():
