@@ -840,24 +840,26 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
         const int t_hi = std::min(t0 + len, n - 1);
         for (int t = t_hi; t >= t0 + 1; --t) {
             const int nxt = (lam == fr[0]) ? fr[1] : fr[0];
+            // Below the last segment, the first step (t = (s+1) k) gathers
+            // S^T nu^{t+1} while snapshot s+1 holds B^t: it also measures the
+            // invariant mark K(t+1) = <nu^{t+1}, S B^t> of snapshot s+1.
+            const bool mark = dL_domega && t == t_hi && s + 1 < segs;
             e = lbm::launch_adjoint_step(ctx->model, ctx->prec, ctx->kp, B[lam], B[nxt],
-                                         segmom + (t - t0 - 1) * L.mom_step, partA, st);
+                                         segmom + (t - t0 - 1) * L.mom_step, partA,
+                                         mark ? ck + (s + 1) * ck_stride : nullptr, partM, st);
+            if (e == hipSuccess && mark)
+                e = lbm::launch_sum_partials(partM, L.nA, 1, 1, dout + 2 + s + 1, st);
             if (e != hipSuccess) return fail_hip(ctx, e, "adjoint step kernel");
             lam = nxt;
         }
-        if (dL_domega) {
-            // invariant mark K(t0 + 1) = <nu^{t0+1}, S B^{t0}>, B^{t0} the snapshot
-            e = lbm::launch_pair_dot(ctx->model, ctx->prec, ctx->kp, ck + s * ck_stride, B[lam],
-                                     partM, st);
-            if (e == hipSuccess) e = lbm::launch_sum_partials(partM, L.nA, 1, 1, dout + 2 + s, st);
-            if (e != hipSuccess) return fail_hip(ctx, e, "invariant kernel");
-        }
     }
     {
-        // dL/dB^0 = S^T nu^1
+        // dL/dB^0 = S^T nu^1; mark K(1) = <nu^1, S B^0> against snapshot 0
         const int nxt = (lam == 0) ? 1 : 0;
         e = lbm::launch_adjoint_step(ctx->model, ctx->prec, ctx->kp, B[lam], B[nxt], nullptr,
-                                     nullptr, st);
+                                     nullptr, dL_domega ? ck : nullptr, partM, st);
+        if (e == hipSuccess && dL_domega)
+            e = lbm::launch_sum_partials(partM, L.nA, 1, 1, dout + 2, st);
         if (e != hipSuccess) return fail_hip(ctx, e, "transposed streaming kernel");
         lam = nxt;
     }

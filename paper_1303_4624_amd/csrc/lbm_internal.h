@@ -113,12 +113,11 @@ hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
 hipError_t launch_lambda_init(ModelId m, Prec p, const KParams& kp, const void* fn,
                               const double* dLdrho, void* lam, double* partK, hipStream_t s);
 // mom == nullptr: transposed streaming only (no collision, partA unused).
+// mark_state != nullptr: also partM[block] = sum_i mu_i B_i over the block's
+// cells, B = mark_state (stored populations, mu the gathered adjoint state).
 hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void* lam_src,
-                               void* lam_dst, const void* mom, double* partA, hipStream_t s);
-// Per-block partial sums of <nu, S state> (state: stored populations, nu: an
-// adjoint state in the same layout), one double per step block.
-hipError_t launch_pair_dot(ModelId m, Prec p, const KParams& kp, const void* state,
-                           const void* nu, double* part, hipStream_t s);
+                               void* lam_dst, const void* mom, double* partA,
+                               const void* mark_state, double* partM, hipStream_t s);
 hipError_t launch_dT_init(ModelId m, Prec p, const KParams& kp, const void* lam0,
                           const double* rho, const double* U, const double* T, double* dT,
                           hipStream_t s);

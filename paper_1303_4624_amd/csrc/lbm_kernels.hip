@@ -399,9 +399,9 @@ __device__ __forceinline__ R edot(R ux, R uy, R uz) {
     return s;
 }
 
-// Sum over a block of K doubles per thread; thread 0 writes (or adds to) out[0..K).
-template <int K>
-__device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accumulate) {
+// Sum over a block of K doubles per thread; thread 0 calls store(q, sum_q).
+template <int K, class Store>
+__device__ __forceinline__ void block_sum_with(double (&v)[K], Store&& store) {
     static_for<K>([&](auto KI) {
         constexpr int q = decltype(KI)::value;
 #pragma unroll
@@ -423,9 +423,15 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accu
             constexpr int q = decltype(KI)::value;
             double s = 0.0;
             for (int w = 0; w < nw; ++w) s += sh[w * K + q];
-            out[q] = accumulate ? out[q] + s : s;
+            store(q, s);
         });
     }
+}
+
+// Sum over a block of K doubles per thread; thread 0 writes (or adds to) out[0..K).
+template <int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* out, bool accumulate) {
+    block_sum_with<K>(v, [&](int q, double s) { out[q] = accumulate ? out[q] + s : s; });
 }
 
 // ---------------------------------------------------------------------------
@@ -773,29 +779,6 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     block_sum<1>(acc, partK + blockIdx.x, false);
 }
 
-// <nu, S B> per cell, summed per block in float64: the adjoint state nu of
-// the pre-collision populations against the streamed stored state S B (the
-// invariant <nu^t, f^t> of the step's homogeneity, measured at checkpoints).
-template <class M, class P>
-__global__ __launch_bounds__(P::max_block) void k_pair_dot(const typename P::S* __restrict__ state,
-                                                           const typename P::S* __restrict__ nu,
-                                                           KParams k, double* __restrict__ part) {
-    using S = typename P::S;
-    const Cell cl = row_cell(k);
-    S v[M::Q];
-    gather<M, +1>(state, k, cl, v);
-    const SlabAddr<M, S, const char> ad(reinterpret_cast<const char*>(nu), k, cl);
-    double acc[1] = {0.0};
-    static_for<M::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
-        const double f = P::shifted ? static_cast<double>(v[i]) + k.W[M::table.group[i]] * k.rho0
-                                    : static_cast<double>(v[i]);
-        acc[0] += static_cast<double>(load_pop<S>(ad.template at<i, 0, 0, 0>())) * f;
-    });
-    if (!cl.active) acc[0] = 0.0;
-    block_sum<1>(acc, part + blockIdx.x, false);
-}
-
 // Derivative coefficients of P = 1 + h with respect to s, u2 and d, per group:
 //   P_s  = a1 + s (2 a2 + s (1/2 + s/6))
 //   P_u2 = b0 + s (-1/2 - s/4),          b0 = -1/2 + u2/4 + d (D + 2 - X)/4
@@ -823,12 +806,18 @@ __device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, do
 //   G_j   = dA/dU / rho - 2 dA/dT U / (D rho),   G_E = dA/dT / (D rho).
 // Output lambda^t_i = omc mu_i + omega (G_rho + G_j . e_i + G_E |e_i|^2).
 // partA[block] += sum over the block's cells of A = rho S0.
-template <class M, class P, bool COLLIDE>
-__global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::adj_waves)))
-void k_adjoint(const typename P::S* __restrict__ lsrc,
-                                                    typename P::S* __restrict__ ldst,
-                                                    const typename P::S* __restrict__ mom,
-                                                    KParams k, double* __restrict__ partA) {
+// MARK: also partM[block] = sum over the block's cells of sum_i mu_i B_i with
+// B the stored state the forward run streamed into f^{t+1} (a checkpoint),
+// i.e. the invariant <lambda^{t+1}, f^{t+1}> of the step's homogeneity.
+// The MARK instances (one step per checkpoint segment) hold the mark's loads
+// as well and are allowed twice the registers (2 waves per SIMD) to avoid
+// spilling.
+template <class M, class P, bool COLLIDE, bool MARK>
+__global__ __launch_bounds__(P::max_block)
+__attribute__((amdgpu_waves_per_eu(MARK ? (P::adj_waves < 2 ? P::adj_waves : 2) : P::adj_waves)))
+void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict__ ldst,
+               const typename P::S* __restrict__ mom, KParams k, double* __restrict__ partA,
+               const typename P::S* __restrict__ mark_state, double* __restrict__ partM) {
     using S = typename P::S;
     using R = S;
     constexpr int Q = M::Q;
@@ -839,10 +828,31 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
     S mu[Q];
     gather<M, -1>(lsrc, k, cl, mu);
 
+    // MARK: mu_i B_i is accumulated where mu_i is consumed (the output loop
+    // of the transposed streaming, the group sums of the collision), so
+    // that the mark's loads do not extend the lifetime of mu.
+    const SlabAddr<M, S, const char> mark_at(reinterpret_cast<const char*>(mark_state), k, cl);
+    double mk = 0.0;
+    const auto mark_term = [&](auto I) {
+        if constexpr (MARK) {
+            constexpr int i = decltype(I)::value;
+            double b = static_cast<double>(load_pop<S>(mark_at.template at<i, 0, 0, 0>()));
+            if constexpr (P::shifted) b += k.W[M::table.group[i]] * k.rho0;
+            mk = fma(static_cast<double>(mu[i]), b, mk);
+        }
+    };
+
     if constexpr (!COLLIDE) {
         // transposed streaming only
         PlaneWriter<S> wt(ldst, k, cl, Q);
-        static_for<Q>([&](auto I) { wt.put(mu[decltype(I)::value]); });
+        static_for<Q>([&](auto I) {
+            mark_term(I);
+            wt.put(mu[decltype(I)::value]);
+        });
+        if constexpr (MARK) {
+            double acc[1] = {cl.active ? mk : 0.0};
+            block_sum<1>(acc, partM + blockIdx.x, false);
+        }
         return;
     }
 
@@ -870,7 +880,7 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
         // sum mu P = sum mu + sum mu h with P = 1 + h: the O(1) part is summed in
         // float64 so that the small omega signal in A is not lost to rounding.
         double tm = 0.0;
-        R t0 = R(0), tu = R(0), td = R(0), tx = R(0), ty = R(0), tz = R(0);
+        R t0 = R(0), tu = R(0), td = R(0), tx = R(0), ty = R(0), tz = R(0), tb = R(0);
         static_for<M::table.gsize[g]>([&](auto JI) {
             constexpr int i = M::table.gstart[g] + decltype(JI)::value;
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
@@ -880,6 +890,7 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
             const R pu = b0 + s * (R(-0.5) - s * R(0.25));
             const R pd = c0 + s * (c1 + s * c2);
             tm += static_cast<double>(mu[i]);
+            if constexpr (MARK) tb = fma(mu[i], load_pop<S>(mark_at.template at<i, 0, 0, 0>()), tb);
             t0 = fma(mu[i], h, t0);
             tu = fma(mu[i], pu, tu);
             td = fma(mu[i], pd, td);
@@ -892,6 +903,12 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
         __builtin_amdgcn_sched_barrier(0);
 #endif
         const double wg = k.W[g];
+        if constexpr (MARK) {
+            // sum_i mu_i B_i of the group: the stored part in storage precision,
+            // the shift w_g rho0 sum_i mu_i from the float64 group sum
+            mk += double(tb);
+            if constexpr (P::shifted) mk = fma(wg * k.rho0, tm, mk);
+        }
         s0 = fma(wg, tm + double(t0), s0);
         su2 = fma(wg, double(tu), su2);
         sd = fma(wg, double(td), sd);
@@ -932,8 +949,16 @@ void k_adjoint(const typename P::S* __restrict__ lsrc,
         out_w.put(fma(omc, mu[i], hv));
     });
 
-    double acc[1] = {cl.active ? rho * s0 : 0.0};
-    block_sum<1>(acc, partA + blockIdx.x, true);
+    if constexpr (MARK) {
+        double acc[2] = {cl.active ? rho * s0 : 0.0, cl.active ? mk : 0.0};
+        block_sum_with<2>(acc, [&](int q, double v) {
+            if (q == 0) partA[blockIdx.x] += v;
+            else partM[blockIdx.x] = v;
+        });
+    } else {
+        double acc[1] = {cl.active ? rho * s0 : 0.0};
+        block_sum<1>(acc, partA + blockIdx.x, true);
+    }
 }
 
 // dL/dT_init(x) = sum_i lambda^0_i(x) d f_i^eq / dT at the initial fields,
@@ -1162,35 +1187,26 @@ hipError_t launch_lambda_init(ModelId m, Prec p, const KParams& kp, const void* 
 }
 
 hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void* lam_src,
-                               void* lam_dst, const void* mom, double* partA, hipStream_t s) {
+                               void* lam_dst, const void* mom, double* partA,
+                               const void* mark_state, double* partM, hipStream_t s) {
     const long long blocks = step_blocks(m, p, kp);
     return with_types(m, p, [&](auto M_, auto P_) {
         using M = decltype(M_);
         using P = decltype(P_);
         using S = typename P::S;
+        const auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kp.bx), 0, s,
+                               static_cast<const S*>(lam_src), static_cast<S*>(lam_dst),
+                               static_cast<const S*>(mom), kp, partA,
+                               static_cast<const S*>(mark_state), partM);
+        };
         if (mom) {
-            hipLaunchKernelGGL((k_adjoint<M, P, true>), dim3(static_cast<unsigned>(blocks)),
-                               dim3(kp.bx), 0, s, static_cast<const S*>(lam_src),
-                               static_cast<S*>(lam_dst), static_cast<const S*>(mom), kp, partA);
+            if (mark_state) go(k_adjoint<M, P, true, true>);
+            else go(k_adjoint<M, P, true, false>);
         } else {
-            hipLaunchKernelGGL((k_adjoint<M, P, false>), dim3(static_cast<unsigned>(blocks)),
-                               dim3(kp.bx), 0, s, static_cast<const S*>(lam_src),
-                               static_cast<S*>(lam_dst), static_cast<const S*>(nullptr), kp,
-                               static_cast<double*>(nullptr));
+            if (mark_state) go(k_adjoint<M, P, false, true>);
+            else go(k_adjoint<M, P, false, false>);
         }
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_pair_dot(ModelId m, Prec p, const KParams& kp, const void* state,
-                           const void* nu, double* part, hipStream_t s) {
-    const long long blocks = step_blocks(m, p, kp);
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        using S = typename P::S;
-        hipLaunchKernelGGL((k_pair_dot<M, P>), dim3(static_cast<unsigned>(blocks)), dim3(kp.bx), 0,
-                           s, static_cast<const S*>(state), static_cast<const S*>(nu), kp, part);
         return hipGetLastError();
     });
 }
