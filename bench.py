@@ -159,9 +159,10 @@ TUBE_PLATEAUS = {"d3q95_11x11x800_tube": ((300, 480), (540, 700)),
                  "d2q33_11x800_tube": ((340, 390), (470, 580))}
 
 
-def run_tube(wname, precision, graph_steps=0):
+def run_tube(wname, precision, graph_steps=0, streaming="ab"):
     """The shock tube with held end planes: time its whole run (optionally
-    replayed in HIP graphs of graph_steps steps, on a side stream)."""
+    replayed in HIP graphs of graph_steps steps, on a side stream; with
+    streaming="aa" in place on one buffer)."""
     import torch
     from paper_1303_4624_amd import Simulation
     from synth_inputs import WORKLOADS, tube_states, workload_ic
@@ -171,7 +172,8 @@ def run_tube(wname, precision, graph_steps=0):
     rho, U, th = workload_ic(w)
     stream = torch.cuda.Stream() if graph_steps else torch.cuda.current_stream()
     with torch.cuda.stream(stream):
-        sim = Simulation(w.model, w.extent, w.omega, precision=precision, stream=stream)
+        sim = Simulation(w.model, w.extent, w.omega, precision=precision, stream=stream,
+                         streaming=streaming)
         sim.init_fields(rho, U, th * sim.T0)
         nh = int(w.extra["hold"])
         sim.set_fixed_planes(nh, nh, (lr,) + (0.0,) * D + (lt * sim.T0,),
@@ -200,6 +202,8 @@ def run_tube(wname, precision, graph_steps=0):
                         "theta_right": round(float(tz[c:d].mean()), 5)}}
     if graph_steps:
         out["graph_steps"] = graph_steps
+    if streaming != "ab":
+        out["streaming"] = streaming
     return out
 
 
@@ -416,6 +420,7 @@ def main():
             for prec in ("fp64", "fp32s"):
                 out[f"{wname}_{prec}"] = run_tube(wname, prec)
                 out[f"{wname}_{prec}_graph"] = run_tube(wname, prec, graph_steps=40)
+            out[f"{wname}_fp32s_aa"] = run_tube(wname, "fp32s", streaming="aa")
         log("[bench] forward + adjoint on 128^3")
         # 128^3 fits many times over in HBM: keep the moments of every segment
         # (no recomputation); the minimum-memory variant keeps one segment.

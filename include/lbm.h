@@ -202,10 +202,11 @@ int lbm_workspace_bytes(const lbm_ctx* ctx, size_t* pop_bytes, size_t* scratch_b
  *     (the update rule that opens the method) and its arithmetic are those
  *     of LBM_STREAM_AB (bit-identical results);
  *     lbm_moments, lbm_conservation and lbm_get/set_populations follow the
- *     alternating storage.  Fixed planes, checkpointed runs and the adjoint
- *     need LBM_STREAM_AB and return LBM_E_UNSUPPORTED.
- * Returns LBM_E_INVALID for another scheme, LBM_E_UNSUPPORTED for
- * LBM_STREAM_AA while planes are held.
+ *     alternating storage, and held planes (lbm_set_fixed_planes) store
+ *     f^eq of their state into the locations they own in either kernel, so
+ *     they too give the LBM_STREAM_AB result bit for bit.  Checkpointed runs
+ *     and the adjoint need LBM_STREAM_AB and return LBM_E_UNSUPPORTED.
+ * Returns LBM_E_INVALID for another scheme.
  */
 int lbm_set_streaming(lbm_ctx* ctx, int scheme);
 
@@ -280,8 +281,8 @@ int lbm_conservation(lbm_ctx* ctx, double* out);
  * The held planes are not touched until the next step (set the initial
  * state with lbm_init_fields).  n_lo = n_hi = 0 restores a fully periodic
  * lattice.  Returns LBM_E_INVALID for n_lo, n_hi < 0, n_lo + n_hi >
- * extent[D-1], NULL or non-positive states, LBM_E_NONFINITE for NaN/Inf,
- * LBM_E_UNSUPPORTED with LBM_STREAM_AA.
+ * extent[D-1], NULL or non-positive states, LBM_E_NONFINITE for NaN/Inf.
+ * Works with both streaming schemes.
  * lbm_run_checkpointed and lbm_adjoint return LBM_E_UNSUPPORTED while
  * planes are held.
  */

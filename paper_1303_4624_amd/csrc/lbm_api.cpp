@@ -527,8 +527,6 @@ LBM_API int lbm_set_fixed_planes(lbm_ctx* ctx, int n_lo, int n_hi, const double*
     const int64_t L = ctx->extent[ctx->D - 1];
     if (n_lo < 0 || n_hi < 0 || static_cast<int64_t>(n_lo) + n_hi > L)
         return fail(ctx, LBM_E_INVALID, "need n_lo, n_hi >= 0 and n_lo + n_hi <= extent[D-1]");
-    if (ctx->aa && n_lo + n_hi > 0)
-        return fail(ctx, LBM_E_UNSUPPORTED, "fixed planes need two-buffer streaming");
     const double* st[2] = {state_lo, state_hi};
     const int cnt[2] = {n_lo, n_hi};
     lbm::FixedState fs[2]{};
@@ -620,8 +618,6 @@ LBM_API int lbm_set_streaming(lbm_ctx* ctx, int scheme) {
     if (scheme != LBM_STREAM_AB && scheme != LBM_STREAM_AA)
         return fail(ctx, LBM_E_INVALID, "scheme must be LBM_STREAM_AB or LBM_STREAM_AA");
     if (ctx->bound) return fail(ctx, LBM_E_STATE, "choose the streaming scheme before lbm_bind");
-    if (scheme == LBM_STREAM_AA && ctx->hold_lo + ctx->hold_hi > 0)
-        return fail(ctx, LBM_E_UNSUPPORTED, "fixed planes need two-buffer streaming");
     ctx->aa = scheme == LBM_STREAM_AA;
     ctx->kp.form = initial_form(ctx);
     return LBM_OK;

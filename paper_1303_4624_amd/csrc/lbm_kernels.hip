@@ -587,12 +587,35 @@ void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ d
 // Every location is read and then written by the same thread only, so the
 // update is race-free in place.  Idle lanes of a ragged row do not store
 // (a duplicate store could overwrite a value before its reader loads it).
-template <class M, class P, bool PUSH>
+// HOLD: cells on the held end planes store f^eq of the held state into the
+// same locations instead of reading them (as k_step<HOLD> does for the
+// two-buffer step), so both schemes hold the same values.
+template <class M, class P, bool PUSH, bool HOLD>
 __global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
 void k_step_aa(typename P::S* f, KParams k) {
     using S = typename P::S;
+    constexpr int D = M::D;
     const Cell cl = row_cell(k);
     const SlabAddr<M, S, char> ad(reinterpret_cast<char*>(f), k, cl);
+    const auto put = [&](auto I, S val) {
+        constexpr int i = decltype(I)::value;
+        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
+        if (cl.active) {
+            if constexpr (PUSH)
+                store_pop<S, LBM_AA_NT_PUSH != 0>(ad.template at<i, ex, ey, ez>(), val);
+            else
+                store_pop<S, LBM_AA_NT_LOCAL != 0>(ad.template at<M::table.opp[i], 0, 0, 0>(), val);
+        }
+    };
+    if constexpr (HOLD) {
+        const int sl = (D == 3) ? cl.z : cl.y;
+        const int L = (D == 3) ? k.nz : k.ny;
+        if (sl < k.hold_lo || sl >= L - k.hold_hi) {
+            const FixedState& st = (sl < k.hold_lo) ? k.hold[0] : k.hold[1];
+            feq_cell<M, P>(k, st.rho, st.U[0], st.U[1], st.U[2], st.T, put);
+            return;
+        }
+    }
     S v[M::Q];
     static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -602,16 +625,7 @@ void k_step_aa(typename P::S* f, KParams k) {
         else
             v[i] = load_pop<S>(ad.template at<i, 0, 0, 0>());
     });
-    relax_cell<M, P>(k, v, [&](auto I, S val) {
-        constexpr int i = decltype(I)::value;
-        constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-        if (cl.active) {
-            if constexpr (PUSH)
-                store_pop<S, LBM_AA_NT_PUSH != 0>(ad.template at<i, ex, ey, ez>(), val);
-            else
-                store_pop<S, LBM_AA_NT_LOCAL != 0>(ad.template at<M::table.opp[i], 0, 0, 0>(), val);
-        }
-    });
+    relax_cell<M, P>(k, v, put);
 }
 
 // ---------------------------------------------------------------------------
@@ -1121,12 +1135,18 @@ hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool pu
         using P = decltype(P_);
         using S = typename P::S;
         const dim3 grid(static_cast<unsigned>(step_blocks(m, p, kp)));
-        if (push)
-            hipLaunchKernelGGL((k_step_aa<M, P, true>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
-                               static_cast<S*>(f), kp);
-        else
-            hipLaunchKernelGGL((k_step_aa<M, P, false>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
-                               static_cast<S*>(f), kp);
+        const auto go = [&](auto kernel) {
+            hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<S*>(f),
+                               kp);
+        };
+        const bool hold = kp.hold_lo + kp.hold_hi > 0;
+        if (push) {
+            if (hold) go(k_step_aa<M, P, true, true>);
+            else go(k_step_aa<M, P, true, false>);
+        } else {
+            if (hold) go(k_step_aa<M, P, false, true>);
+            else go(k_step_aa<M, P, false, false>);
+        }
         return hipGetLastError();
     });
 }

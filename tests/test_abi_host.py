@@ -193,16 +193,13 @@ def test_streaming_scheme_validation():
         with pytest.raises(L.LBMError) as ex:
             L.lbm_set_streaming(ctx, 2)
         assert ex.value.status == L.LBM_E_INVALID
+        # held planes work with either scheme, in either order
         L.lbm_set_streaming(ctx, L.LBM_STREAM_AA)
-        with pytest.raises(L.LBMError) as ex:
-            L.lbm_set_fixed_planes(ctx, 5, 5, good, good)
-        assert ex.value.status == L.LBM_E_UNSUPPORTED
-        L.lbm_set_fixed_planes(ctx, 0, 0)           # clearing is always allowed
-        L.lbm_set_streaming(ctx, L.LBM_STREAM_AB)
         L.lbm_set_fixed_planes(ctx, 5, 5, good, good)
-        with pytest.raises(L.LBMError) as ex:
-            L.lbm_set_streaming(ctx, L.LBM_STREAM_AA)
-        assert ex.value.status == L.LBM_E_UNSUPPORTED
+        L.lbm_set_streaming(ctx, L.LBM_STREAM_AB)
+        L.lbm_set_streaming(ctx, L.LBM_STREAM_AA)
+        L.lbm_set_fixed_planes(ctx, 0, 0)
+        L.lbm_set_streaming(ctx, L.LBM_STREAM_AB)
         pop, _ = L.lbm_workspace_bytes(ctx)
         assert pop == 95 * 6 * 4 * 20 * 8
     finally:

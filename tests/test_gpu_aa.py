@@ -7,7 +7,7 @@ import torch
 
 from gpu_helpers import oracle_run, rel_errors
 from paper_1303_4624_amd import Simulation, _lib as L
-from synth_inputs import smooth_ic
+from synth_inputs import WORKLOADS, smooth_ic, tube_states, workload_ic
 
 pytestmark = pytest.mark.gpu
 
@@ -89,15 +89,73 @@ def test_in_place_matches_oracle_and_set_populations(model, extent):
         aa.close()
 
 
+@pytest.mark.parametrize("model,extent,n_lo,n_hi", [
+    ("D3Q95", (5, 3, 40), 5, 5),
+    ("D3Q95", (7, 2, 33), 5, 2),      # thinner than the stencil at the top
+    ("D3Q95", (300, 2, 24), 0, 5),    # one held end; two chunks per row, ragged tail
+    ("D2Q33", (7, 33), 4, 4),
+    ("D2Q33", (5, 28), 3, 0),
+])
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_in_place_with_held_planes_equals_two_buffer_bitwise(model, extent, n_lo, n_hi,
+                                                             precision):
+    # The held cells store f^eq of their state into the locations they own in
+    # either storage form; waves from the centre reach the held planes.
+    _say("case", model, extent, n_lo, n_hi, precision)
+    D = len(extent)
+    rho, U, th = _ic(extent, 61)
+    ab, aa = _pair(model, extent, precision, omega=1.4)
+    try:
+        lo = (2.0,) + (0.0,) * D + (1.0 * ab.T0,)
+        hi = (1.0,) + (0.01,) * D + (1.1 * ab.T0,)
+        for s in (ab, aa):
+            s.init_fields(rho, U, th * s.T0)
+            s.set_fixed_planes(n_lo, n_hi, lo, hi)
+        for n in (1, 1, 2, 5, 8):          # both storage forms
+            ab.step(n)
+            aa.step(n)
+            _same(ab, aa)
+        for s in (ab, aa):                 # back to periodic, in the pushed form
+            s.set_fixed_planes(0, 0)
+        for n in (3, 2):
+            ab.step(n)
+            aa.step(n)
+            _same(ab, aa)
+    finally:
+        ab.close()
+        aa.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_paper_tube_in_place_equals_two_buffer_bitwise(precision):
+    w = WORKLOADS["d3q95_11x11x800_tube"]
+    _say("case", w.name, precision)
+    (lr, lt), (rr, rt) = tube_states(w)
+    nh = int(w.extra["hold"])
+    rho, U, th = workload_ic(w)
+    ab, aa = _pair(w.model, w.extent, precision, omega=w.omega)
+    try:
+        for s in (ab, aa):
+            s.init_fields(rho, U, th * s.T0)
+            s.set_fixed_planes(nh, nh, (lr, 0.0, 0.0, 0.0, lt * s.T0),
+                               (rr, 0.0, 0.0, 0.0, rt * s.T0))
+            s.step(w.steps - 1)
+        _same(ab, aa)
+        ab.step(1)
+        aa.step(1)
+        _same(ab, aa)
+    finally:
+        ab.close()
+        aa.close()
+
+
 def test_in_place_refuses_what_needs_two_buffers():
     ext = (8, 6, 20)
     rho, U, th = _ic(ext)
     aa = Simulation("D3Q95", ext, 1.3, precision="fp64", streaming="aa")
     try:
         aa.init_fields(rho, U, th * aa.T0)
-        st = (1.0, 0.0, 0.0, 0.0, aa.T0)
-        for fn in (lambda: aa.set_fixed_planes(5, 5, st, st),
-                   lambda: aa.run_checkpointed(4, 2),
+        for fn in (lambda: aa.run_checkpointed(4, 2),
                    lambda: aa.adjoint(4, 2, torch.zeros(8, dtype=torch.float64, device="cuda"),
                                       rho, U, th * aa.T0, np.ones_like(rho))):
             with pytest.raises(L.LBMError) as ex:
