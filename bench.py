@@ -207,14 +207,15 @@ def run_tube(wname, precision, graph_steps=0, streaming="ab"):
     return out
 
 
-def run_fwd_adjoint(extent, omega, n, k, keep=1):
+def run_fwd_adjoint(extent, omega, n, k, keep=1, streaming="ab"):
     """Wall time of the checkpointed forward run and of the adjoint, same stream.
-    `keep`: trailing segments whose step moments the forward run keeps."""
+    `keep`: trailing segments whose step moments the forward run keeps;
+    `streaming`: "aa" runs the forward pass in place on one buffer."""
     import torch
     from paper_1303_4624_amd import Simulation
     from synth_inputs import smooth_ic, target_theta
     rho, U, th = smooth_ic(extent)
-    sim = Simulation("D3Q95", extent, omega, precision="fp32s")
+    sim = Simulation("D3Q95", extent, omega, precision="fp32s", streaming=streaming)
     T = th * sim.T0
     sim.init_fields(rho, U, target_theta(extent) * sim.T0)
     sim.step(n)
@@ -248,6 +249,8 @@ def run_fwd_adjoint(extent, omega, n, k, keep=1):
     res["ratio_total_over_fwd"] = (res["fwd_ms"] + res["bwd_ms"]) / res["fwd_ms"]
     res["ratio_total_over_plain_fwd"] = (res["fwd_ms"] + res["bwd_ms"]) / res["plain_fwd_ms"]
     res["grid"] = list(extent)
+    if streaming != "ab":
+        res["streaming"] = streaming
     res["steps"] = n
     res["checkpoint_every"] = k
     res["kept_segments"] = keep
@@ -427,6 +430,8 @@ def main():
         out["fwd_adjoint_128c"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20, keep=10)
         out["fwd_adjoint_128c_min_memory"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20,
                                                              keep=1)
+        out["fwd_adjoint_128c_in_place"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20,
+                                                           keep=10, streaming="aa")
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
         out["cpu_baseline"] = cpu_oracle_baseline()

@@ -204,8 +204,10 @@ int lbm_workspace_bytes(const lbm_ctx* ctx, size_t* pop_bytes, size_t* scratch_b
  *     lbm_moments, lbm_conservation and lbm_get/set_populations follow the
  *     alternating storage, and held planes (lbm_set_fixed_planes) store
  *     f^eq of their state into the locations they own in either kernel, so
- *     they too give the LBM_STREAM_AB result bit for bit.  Checkpointed runs
- *     and the adjoint need LBM_STREAM_AB and return LBM_E_UNSUPPORTED.
+ *     they too give the LBM_STREAM_AB result bit for bit.
+ *     lbm_run_checkpointed copies its snapshots out of the buffer in the
+ *     LBM_STREAM_AB layout, so lbm_adjoint works with either scheme and
+ *     gives the same gradients bit for bit.
  * Returns LBM_E_INVALID for another scheme.
  */
 int lbm_set_streaming(lbm_ctx* ctx, int scheme);
@@ -322,7 +324,8 @@ int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, int keep, size_t* byt
  * segment) in slot s = t/k, the final state in slot ceil(n/k), and after the
  * slots the moments of every step of the last `keep` segments.  Snapshot 0
  * is a copy of the bound state; later snapshots are written in place by the
- * step that produces them.
+ * step that produces them (LBM_STREAM_AA: every snapshot and the final state
+ * are copied out of the in-place buffer in the two-buffer layout).
  * n >= 1, k >= 1, keep >= 1.
  */
 int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckpt, size_t ckpt_bytes);

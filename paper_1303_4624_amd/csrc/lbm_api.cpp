@@ -362,7 +362,8 @@ hipError_t launch_one_step(lbm_ctx* ctx) {
     if (ctx->aa) {
         const bool push = ctx->kp.form == lbm::kFormSwapped;
         hipError_t e =
-            lbm::launch_step_aa(ctx->model, ctx->prec, ctx->kp, ctx->f[0], push, ctx->stream);
+            lbm::launch_step_aa(ctx->model, ctx->prec, ctx->kp, ctx->f[0], push, nullptr,
+                                ctx->stream);
         if (e == hipSuccess) ctx->kp.form = push ? lbm::kFormPushed : lbm::kFormSwapped;
         return e;
     }
@@ -676,14 +677,35 @@ LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckp
     if (ctx->hold_lo + ctx->hold_hi > 0)
         return fail(ctx, LBM_E_UNSUPPORTED, "checkpointed runs need an all-periodic lattice "
                                             "(fixed planes are set)");
-    if (ctx->aa)
-        return fail(ctx, LBM_E_UNSUPPORTED, "checkpointed runs need two-buffer streaming");
     const CkLayout c = ck_layout(ctx, n, k, keep);
     if (ckpt_bytes < c.total) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
     if ((rc = check_dev(ctx, ckpt, c.total, "ckpt")) != LBM_OK) return rc;
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
     const size_t pb = pop_bytes(ctx);
     char* ck = static_cast<char*>(ckpt);
+    if (ctx->aa) {
+        // In place: the state stays in the bound buffer; snapshot 0, each
+        // later snapshot and the final state are copied out of it in the
+        // two-buffer form, so the adjoint reads the same checkpoints.
+        hipError_t e = lbm::launch_to_ab(ctx->model, ctx->prec, ctx->kp, ctx->f[0], ck, ctx->stream);
+        if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy kernel");
+        for (int t = 0; t < n; ++t) {
+            void* mom = (t >= c.t_keep) ? ck + c.off_tail + (t - c.t_keep) * c.mom_step : nullptr;
+            const bool push = ctx->kp.form == lbm::kFormSwapped;
+            e = lbm::launch_step_aa(ctx->model, ctx->prec, ctx->kp, ctx->f[0], push, mom,
+                                    ctx->stream);
+            if (e != hipSuccess) return fail_hip(ctx, e, "in-place step kernel");
+            ctx->kp.form = push ? lbm::kFormPushed : lbm::kFormSwapped;
+            char* slot = nullptr;
+            if (t + 1 == n) slot = ck + c.off_final;
+            else if ((t + 1) % k == 0) slot = ck + ((t + 1) / k) * c.stride;
+            if (slot) {
+                e = lbm::launch_to_ab(ctx->model, ctx->prec, ctx->kp, ctx->f[0], slot, ctx->stream);
+                if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint copy kernel");
+            }
+        }
+        return LBM_OK;
+    }
     // Snapshot 0 is a copy (the adjoint recomputes segment 0 from it, or
     // measures its invariant there); every later snapshot is written directly
     // by the step that ends the previous segment, and the next step reads it
@@ -759,7 +781,6 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
     if (ctx->hold_lo + ctx->hold_hi > 0)
         return fail(ctx, LBM_E_UNSUPPORTED, "the adjoint needs an all-periodic lattice "
                                             "(fixed planes are set)");
-    if (ctx->aa) return fail(ctx, LBM_E_UNSUPPORTED, "the adjoint needs two-buffer streaming");
     if (dL_domega && std::fabs(1.0 - ctx->omega) < 1e-3)
         return fail(ctx, LBM_E_INVALID,
                     "the omega gradient needs |1 - omega| >= 1e-3 (it is divided by 1 - omega)");
@@ -782,6 +803,10 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
         return fail(ctx, LBM_E_INVALID, "workspace must be 256-byte aligned");
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
 
+    // The checkpoints and the adjoint's buffers are in the two-buffer form,
+    // whatever scheme the forward run used.
+    lbm::KParams kab = ctx->kp;
+    kab.form = lbm::kFormAB;
     char* ws = static_cast<char*>(workspace);
     void* B[3] = {ws, ws + L.pop, ws + 2 * L.pop};
     char* mom = ws + L.off_mom;
@@ -812,7 +837,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
         if (lam < 0) {
             // start from f*(n), kept by the forward run
             lam = fr[0];
-            e = lbm::launch_lambda_init(ctx->model, ctx->prec, ctx->kp, ck + C.off_final,
+            e = lbm::launch_lambda_init(ctx->model, ctx->prec, kab, ck + C.off_final,
                                         dL_drho_final, B[lam], partK, st);
             if (e != hipSuccess) return fail_hip(ctx, e, "adjoint initialisation kernel");
             fr[0] = 2;   // the free pair is now {1, 2}
@@ -826,7 +851,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
             const void* src = ck + s * ck_stride;
             int dst = fr[0];
             for (int j = 0; j < len; ++j) {
-                e = lbm::launch_step(ctx->model, ctx->prec, ctx->kp, src, B[dst],
+                e = lbm::launch_step(ctx->model, ctx->prec, kab, src, B[dst],
                                      mom + j * L.mom_step, st);
                 if (e != hipSuccess) return fail_hip(ctx, e, "recompute step kernel");
                 src = B[dst];
@@ -840,7 +865,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
             // S^T nu^{t+1} while snapshot s+1 holds B^t: it also measures the
             // invariant mark K(t+1) = <nu^{t+1}, S B^t> of snapshot s+1.
             const bool mark = dL_domega && t == t_hi && s + 1 < segs;
-            e = lbm::launch_adjoint_step(ctx->model, ctx->prec, ctx->kp, B[lam], B[nxt],
+            e = lbm::launch_adjoint_step(ctx->model, ctx->prec, kab, B[lam], B[nxt],
                                          segmom + (t - t0 - 1) * L.mom_step, partA,
                                          mark ? ck + (s + 1) * ck_stride : nullptr, partM, st);
             if (e == hipSuccess && mark)
@@ -852,7 +877,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
     {
         // dL/dB^0 = S^T nu^1; mark K(1) = <nu^1, S B^0> against snapshot 0
         const int nxt = (lam == 0) ? 1 : 0;
-        e = lbm::launch_adjoint_step(ctx->model, ctx->prec, ctx->kp, B[lam], B[nxt], nullptr,
+        e = lbm::launch_adjoint_step(ctx->model, ctx->prec, kab, B[lam], B[nxt], nullptr,
                                      nullptr, dL_domega ? ck : nullptr, partM, st);
         if (e == hipSuccess && dL_domega)
             e = lbm::launch_sum_partials(partM, L.nA, 1, 1, dout + 2, st);
@@ -860,7 +885,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
         lam = nxt;
     }
     if (dL_dT_init) {
-        e = lbm::launch_dT_init(ctx->model, ctx->prec, ctx->kp, B[lam], rho_init, U_init, T_init,
+        e = lbm::launch_dT_init(ctx->model, ctx->prec, kab, B[lam], rho_init, U_init, T_init,
                                 dL_dT_init, st);
         if (e != hipSuccess) return fail_hip(ctx, e, "temperature gradient kernel");
     }

@@ -102,9 +102,13 @@ hipError_t launch_get_pop(ModelId m, Prec p, const KParams& kp, const void* f, d
 hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, void* dst,
                        void* mom_out, hipStream_t s);
 // In-place step (AA pattern): push = true reads the swapped form and writes
-// the pushed form, push = false the reverse.
+// the pushed form, push = false the reverse.  mom_out != nullptr: also store
+// the step's D+2 moments (as launch_step does; fixed planes are then ignored).
 hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool push,
-                          hipStream_t s);
+                          void* mom_out, hipStream_t s);
+// Copy of the state f, stored in form kp.form, into the two-buffer form.
+hipError_t launch_to_ab(ModelId m, Prec p, const KParams& kp, const void* f, void* out,
+                        hipStream_t s);
 hipError_t launch_moments(ModelId m, Prec p, const KParams& kp, const void* f, double* rho,
                           double* U, double* T, hipStream_t s);
 hipError_t launch_conservation(ModelId m, Prec p, const KParams& kp, const void* f,

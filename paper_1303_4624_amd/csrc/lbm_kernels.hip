@@ -590,9 +590,10 @@ void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ d
 // HOLD: cells on the held end planes store f^eq of the held state into the
 // same locations instead of reading them (as k_step<HOLD> does for the
 // two-buffer step), so both schemes hold the same values.
-template <class M, class P, bool PUSH, bool HOLD>
+// STORE_MOM: also store the step's D+2 moments, as k_step<STORE_MOM> does.
+template <class M, class P, bool PUSH, bool HOLD, bool STORE_MOM>
 __global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
-void k_step_aa(typename P::S* f, KParams k) {
+void k_step_aa(typename P::S* f, KParams k, typename P::S* __restrict__ mom) {
     using S = typename P::S;
     constexpr int D = M::D;
     const Cell cl = row_cell(k);
@@ -625,7 +626,16 @@ void k_step_aa(typename P::S* f, KParams k) {
         else
             v[i] = load_pop<S>(ad.template at<i, 0, 0, 0>());
     });
-    relax_cell<M, P>(k, v, put);
+    const Macro mc = relax_cell<M, P>(k, v, put);
+    if constexpr (STORE_MOM) {
+        if (cl.active) {
+            mom[cl.c] = S(P::shifted ? mc.dr : mc.rho);
+            mom[k.N + cl.c] = S(mc.ux);
+            mom[2 * k.N + cl.c] = S(mc.uy);
+            if constexpr (D == 3) mom[3 * k.N + cl.c] = S(mc.uz);
+            mom[(D + 1) * k.N + cl.c] = S(mc.d);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -670,6 +680,21 @@ __global__ __launch_bounds__(kBlock) void k_get_pop(const typename P::S* __restr
         constexpr int g = M::table.group[i];
         const double val = static_cast<double>(f[pa.template at<i>()]);
         fout[static_cast<long long>(i) * k.N + c] = P::shifted ? val + k.W[g] * k.rho0 : val;
+    });
+}
+
+// Copy of a stored state in form FORM into the two-buffer form (same
+// storage type, bit for bit).
+template <class M, class P, int FORM>
+__global__ __launch_bounds__(kBlock) void k_to_ab(const typename P::S* __restrict__ f,
+                                                  typename P::S* __restrict__ out, KParams k) {
+    const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= k.N) return;
+    const PopAt<M, FORM> src(k, c);
+    const PopAt<M, kFormAB> dst(k, c);
+    static_for<M::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        out[dst.template at<i>()] = f[src.template at<i>()];
     });
 }
 
@@ -1129,7 +1154,7 @@ hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, vo
 }
 
 hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool push,
-                          hipStream_t s) {
+                          void* mom_out, hipStream_t s) {
     return with_types(m, p, [&](auto M_, auto P_) {
         using M = decltype(M_);
         using P = decltype(P_);
@@ -1137,17 +1162,34 @@ hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool pu
         const dim3 grid(static_cast<unsigned>(step_blocks(m, p, kp)));
         const auto go = [&](auto kernel) {
             hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<S*>(f),
-                               kp);
+                               kp, static_cast<S*>(mom_out));
         };
         const bool hold = kp.hold_lo + kp.hold_hi > 0;
         if (push) {
-            if (hold) go(k_step_aa<M, P, true, true>);
-            else go(k_step_aa<M, P, true, false>);
+            if (mom_out) go(k_step_aa<M, P, true, false, true>);
+            else if (hold) go(k_step_aa<M, P, true, true, false>);
+            else go(k_step_aa<M, P, true, false, false>);
         } else {
-            if (hold) go(k_step_aa<M, P, false, true>);
-            else go(k_step_aa<M, P, false, false>);
+            if (mom_out) go(k_step_aa<M, P, false, false, true>);
+            else if (hold) go(k_step_aa<M, P, false, true, false>);
+            else go(k_step_aa<M, P, false, false, false>);
         }
         return hipGetLastError();
+    });
+}
+
+hipError_t launch_to_ab(ModelId m, Prec p, const KParams& kp, const void* f, void* out,
+                        hipStream_t s) {
+    return with_types(m, p, [&](auto M_, auto P_) {
+        using M = decltype(M_);
+        using P = decltype(P_);
+        using S = typename P::S;
+        return with_form(kp, [&](auto F) {
+            hipLaunchKernelGGL((k_to_ab<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                               dim3(kBlock), 0, s, static_cast<const S*>(f), static_cast<S*>(out),
+                               kp);
+            return hipGetLastError();
+        });
     });
 }
 

@@ -149,18 +149,70 @@ def test_paper_tube_in_place_equals_two_buffer_bitwise(precision):
         aa.close()
 
 
-def test_in_place_refuses_what_needs_two_buffers():
+@pytest.mark.parametrize("model,extent,n,k,keep,precision,pre", [
+    ("D3Q95", (20, 10, 8), 10, 3, 1, "fp32s", 0),
+    ("D3Q95", (20, 10, 8), 10, 3, 99, "fp64", 1),    # starts in the pushed form
+    ("D2Q33", (20, 12), 13, 4, 2, "fp32s", 1),
+    ("D3Q95", (7, 5, 4), 3, 2, 1, "fp64", 2),
+])
+def test_in_place_checkpoints_and_adjoint_equal_two_buffer_bitwise(model, extent, n, k, keep,
+                                                                   precision, pre):
+    # The in-place run copies its snapshots out in the two-buffer form and
+    # stores the same moments, so the adjoint sees the same checkpoints.
+    _say("case", model, extent, n, k, keep, precision, pre)
+    rho, U, th = _ic(extent, 41)
+    tgt = 1.0 + 0.01 * smooth_ic(extent, seeds=tuple(range(51, 51 + len(extent) + 2)))[0]
+    ab, aa = _pair(model, extent, precision, omega=1.3)
+    try:
+        out = []
+        for s in (ab, aa):
+            T = th * s.T0
+            s.init_fields(rho, U, T)
+            s.step(pre)
+            r0, u0, t0 = [x.clone() for x in s.moments()]
+            ck = s.run_checkpointed(n, k, keep)
+            r = s.moments()[0]
+            g = 2.0 * (r - torch.as_tensor(tgt, device=r.device))
+            dT, dw = s.adjoint(n, k, ck, r0, u0, t0, g, keep=keep)
+            out.append((s.get_populations(), dT, dw))
+        (fa, dTa, dwa), (fb, dTb, dwb) = out
+        _say("dL/domega", dwa, dwb)
+        assert torch.equal(fa, fb) and torch.equal(dTa, dTb) and dwa == dwb
+        _same(ab, aa)
+    finally:
+        ab.close()
+        aa.close()
+
+
+def test_in_place_lbmfunction_matches_oracle():
+    from oracle import lbm as olbm, velocity_sets as ovs
+    from paper_1303_4624_amd import LBMFunction
+    extent, n, k = (16, 8, 8), 10, 4
+    rho, U, th = _ic(extent, 11)
+    v = ovs.velocity_set("D3Q95")
+    target = np.full(rho.shape, 1.0)
+    _, gT_o, gw_o = olbm.loss_and_grad(v, rho, U, th * v.T0, 1.3, n, target)
+    sim = Simulation("D3Q95", extent, 1.3, precision="fp64", streaming="aa")
+    try:
+        T = torch.tensor(th * sim.T0, device="cuda", requires_grad=True)
+        w = torch.tensor(1.3, dtype=torch.float64, device="cuda", requires_grad=True)
+        r = LBMFunction.apply(T, w, sim, torch.tensor(rho, device="cuda"),
+                              torch.tensor(U, device="cuda"), n, k, 1)
+        ((r - 1.0) ** 2).sum().backward()
+        eT = np.max(np.abs(T.grad.cpu().numpy() - gT_o.numpy())) / np.max(np.abs(gT_o.numpy()))
+        ew = abs(float(w.grad) - gw_o) / abs(gw_o)
+        _say("errors", eT, ew)
+        assert eT <= 1e-9 and ew <= 1e-9
+    finally:
+        sim.close()
+
+
+def test_in_place_scheme_is_chosen_before_bind():
     ext = (8, 6, 20)
     rho, U, th = _ic(ext)
     aa = Simulation("D3Q95", ext, 1.3, precision="fp64", streaming="aa")
     try:
         aa.init_fields(rho, U, th * aa.T0)
-        for fn in (lambda: aa.run_checkpointed(4, 2),
-                   lambda: aa.adjoint(4, 2, torch.zeros(8, dtype=torch.float64, device="cuda"),
-                                      rho, U, th * aa.T0, np.ones_like(rho))):
-            with pytest.raises(L.LBMError) as ex:
-                fn()
-            assert ex.value.status == L.LBM_E_UNSUPPORTED
         with pytest.raises(L.LBMError) as ex:
             L.lbm_set_streaming(aa.ctx, L.LBM_STREAM_AB)    # already bound
         assert ex.value.status == L.LBM_E_STATE
