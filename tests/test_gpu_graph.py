@@ -57,12 +57,13 @@ def test_graph_replay_equals_single_launches(model, extent, precision, streaming
             graph.close()
 
 
-def test_graph_replay_with_held_planes():
+@pytest.mark.parametrize("streaming", ["ab", "aa"])
+def test_graph_replay_with_held_planes(streaming):
     extent = (6, 4, 40)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         rho, U, th = tube_ic(extent, 20, (2.0, 1.0), (1.0, 1.1))
-        plain, graph = _pair("D3Q95", extent, "fp64", "ab", stream)
+        plain, graph = _pair("D3Q95", extent, "fp64", streaming, stream)
         try:
             for s in (plain, graph):
                 s.init_fields(rho, U, th * s.T0)
