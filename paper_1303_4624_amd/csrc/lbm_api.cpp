@@ -50,6 +50,33 @@ struct lbm_ctx {
     std::string err;
 };
 
+namespace lbm {
+
+// Launch geometry (host only; the kernels' launch bounds are the same macros).
+int step_max_threads(Prec p) { return p == Prec::F64 ? LBM_F64_MAXB : LBM_STEP_MAXB; }
+
+RowLaunch row_launch(int nx, long long rows, int max_threads) {
+    RowLaunch r;
+    r.chunks = (nx + max_threads - 1) / max_threads;
+    const int per = (nx + r.chunks - 1) / r.chunks;
+    r.bx = ((per + 63) / 64) * 64;
+    r.blocks = rows * r.chunks;
+    return r;
+}
+
+int reduce_blocks(long long N) {
+    long long b = (N + kReduceThreads - 1) / kReduceThreads;
+    if (b > 1024) b = 1024;
+    if (b < 1) b = 1;
+    return static_cast<int>(b);
+}
+
+long long step_blocks(ModelId, Prec, const KParams& kp) {
+    return static_cast<long long>(kp.ny) * kp.nz * kp.chunks;
+}
+
+}  // namespace lbm
+
 namespace {
 
 thread_local std::string g_err;

@@ -9,6 +9,15 @@
 
 #include "lbm_model.h"
 
+// Largest block of the row-blocked kernels (launch bounds): float32 storage,
+// float64 storage.
+#ifndef LBM_STEP_MAXB
+#define LBM_STEP_MAXB 512
+#endif
+#ifndef LBM_F64_MAXB
+#define LBM_F64_MAXB 256
+#endif
+
 namespace lbm {
 
 // Per-context constants, passed to every kernel by value.

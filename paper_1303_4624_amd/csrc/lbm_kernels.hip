@@ -44,12 +44,6 @@
 namespace lbm {
 namespace {
 
-#ifndef LBM_STEP_MAXB
-#define LBM_STEP_MAXB 512
-#endif
-#ifndef LBM_F64_MAXB
-#define LBM_F64_MAXB 256
-#endif
 #ifndef LBM_NT_STORE
 #define LBM_NT_STORE 1
 #endif
@@ -1051,28 +1045,9 @@ inline unsigned cell_blocks(long long N) {
 
 }  // namespace
 
-int step_max_threads(Prec p) { return p == Prec::F64 ? F64T::max_block : F32ST::max_block; }
-
-RowLaunch row_launch(int nx, long long rows, int max_threads) {
-    RowLaunch r;
-    const int maxb = max_threads;
-    r.chunks = (nx + maxb - 1) / maxb;
-    const int per = (nx + r.chunks - 1) / r.chunks;
-    r.bx = ((per + 63) / 64) * 64;
-    r.blocks = rows * r.chunks;
-    return r;
-}
-
-int reduce_blocks(long long N) {
-    long long b = (N + kBlock - 1) / kBlock;
-    if (b > 1024) b = 1024;
-    if (b < 1) b = 1;
-    return static_cast<int>(b);
-}
-
-long long step_blocks(ModelId, Prec, const KParams& kp) {
-    return static_cast<long long>(kp.ny) * kp.nz * kp.chunks;
-}
+static_assert(F64T::max_block == LBM_F64_MAXB && F32ST::max_block == LBM_STEP_MAXB,
+              "step_max_threads (host) and the kernels' launch bounds must agree");
+static_assert(kBlock == kReduceThreads, "reduce_blocks (host) assumes kBlock threads");
 
 // Calls f with std::integral_constant<int, kp.form>.
 template <class F>
