@@ -331,6 +331,23 @@ int lbm_checkpoint_bytes(const lbm_ctx* ctx, int n, int k, int keep, size_t* byt
 int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckpt, size_t ckpt_bytes);
 
 /*
+ * lbm_restore_checkpoint - resume a run from a checkpoint buffer filled by
+ * lbm_run_checkpointed(n, k, keep) of a context with the same model, grid,
+ * precision and rho0 (checkpoint/resume; the state is the one the update
+ * rule advances).
+ *   slot : 0 .. ceil(n/k) - 1 restores the stored state at t = slot*k;
+ *          ceil(n/k) restores the final state at t = n.
+ * The snapshot is copied into the bound populations (in place: into the
+ * in-place form), so lbm_step(m) then continues exactly as the original run
+ * did, bit for bit, with the context's current omega.  Asynchronous on the
+ * stream; the buffer must stay valid until the copy has run.
+ * LBM_E_STATE before lbm_bind; LBM_E_INVALID for n, k, keep < 1, a slot out
+ * of range or a buffer smaller than lbm_checkpoint_bytes(n, k, keep).
+ */
+int lbm_restore_checkpoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
+                           size_t ckpt_bytes, int slot);
+
+/*
  * lbm_adjoint_workspace_bytes - size of the workspace lbm_adjoint needs for
  * the same (n, k, keep): three population-sized buffers (adjoint ping-pong
  * and recomputation), k steps of stored moments when some segment is

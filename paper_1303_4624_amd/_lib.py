@@ -33,7 +33,7 @@ EXPORTED = [
     "lbm_velocity_set", "lbm_equation_count", "lbm_model_build", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments",
     "lbm_conservation", "lbm_set_fixed_planes", "lbm_set_streaming", "lbm_set_graph_steps",
-    "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed",
+    "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed", "lbm_restore_checkpoint",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_str",
     "lbm_last_error",
 ]
@@ -75,6 +75,8 @@ _SIGS = {
     "lbm_set_omega": (_c.c_int, [_vp, _c.c_double]),
     "lbm_checkpoint_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _psz]),
     "lbm_run_checkpointed": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _vp, _sz]),
+    "lbm_restore_checkpoint": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _vp, _sz,
+                                          _c.c_int]),
     "lbm_adjoint_workspace_bytes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _psz]),
     "lbm_adjoint": (_c.c_int, [_vp, _c.c_int, _c.c_int, _c.c_int, _vp, _sz, _vp, _vp, _vp, _vp,
                                _vp, _sz, _vp, _pd]),
@@ -252,6 +254,13 @@ def lbm_checkpoint_bytes(ctx, n: int, k: int, keep: int = 1) -> int:
 def lbm_run_checkpointed(ctx, n: int, k: int, keep: int, ckpt, ckpt_bytes: int) -> None:
     _check(library().lbm_run_checkpointed(ctx, int(n), int(k), int(keep), _addr(ckpt),
                                           int(ckpt_bytes)), "lbm_run_checkpointed", ctx)
+
+
+def lbm_restore_checkpoint(ctx, n: int, k: int, keep: int, ckpt, ckpt_bytes: int,
+                           slot: int) -> None:
+    _check(library().lbm_restore_checkpoint(ctx, int(n), int(k), int(keep), _addr(ckpt),
+                                            int(ckpt_bytes), int(slot)),
+           "lbm_restore_checkpoint", ctx)
 
 
 def lbm_adjoint_workspace_bytes(ctx, n: int, k: int, keep: int = 1) -> int:

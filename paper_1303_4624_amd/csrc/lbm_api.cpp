@@ -756,6 +756,32 @@ LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckp
     return LBM_OK;
 }
 
+LBM_API int lbm_restore_checkpoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
+                                   size_t ckpt_bytes, int slot) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (!ctx->bound) return fail(ctx, LBM_E_STATE, "no buffers bound (call lbm_bind)");
+    if (n < 1 || k < 1 || keep < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
+    const CkLayout c = ck_layout(ctx, n, k, keep);
+    if (slot < 0 || slot > c.segs)
+        return fail(ctx, LBM_E_INVALID, "slot must be in [0, ceil(n/k)] (the last: final state)");
+    if (ckpt_bytes < c.total) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
+    int rc;
+    if ((rc = check_dev(ctx, ckpt, c.total, "ckpt")) != LBM_OK) return rc;
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    const char* src = static_cast<const char*>(ckpt) +
+                      (slot == c.segs ? c.off_final : static_cast<size_t>(slot) * c.stride);
+    KParams kp = ctx->kp;
+    kp.form = initial_form(ctx);
+    hipError_t e =
+        ctx->aa ? lbm::launch_from_ab(ctx->model, ctx->prec, kp, src, ctx->f[0], ctx->stream)
+                : hipMemcpyAsync(ctx->f[ctx->cur], src, pop_bytes(ctx), hipMemcpyDeviceToDevice,
+                                 ctx->stream);
+    if (e != hipSuccess) return fail_hip(ctx, e, "checkpoint restore");
+    ctx->kp.form = kp.form;
+    ctx->initialized = true;
+    return LBM_OK;
+}
+
 namespace {
 
 // Adjoint workspace: [three adjoint-state buffers][moments of one recomputed

@@ -118,6 +118,9 @@ hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool pu
 // Copy of the state f, stored in form kp.form, into the two-buffer form.
 hipError_t launch_to_ab(ModelId m, Prec p, const KParams& kp, const void* f, void* out,
                         hipStream_t s);
+// Copy of the two-buffer-form state f into form kp.form (two-buffer or swapped).
+hipError_t launch_from_ab(ModelId m, Prec p, const KParams& kp, const void* f, void* out,
+                          hipStream_t s);
 hipError_t launch_moments(ModelId m, Prec p, const KParams& kp, const void* f, double* rho,
                           double* U, double* T, hipStream_t s);
 hipError_t launch_conservation(ModelId m, Prec p, const KParams& kp, const void* f,

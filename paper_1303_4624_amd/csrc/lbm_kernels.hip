@@ -692,6 +692,20 @@ __global__ __launch_bounds__(kBlock) void k_to_ab(const typename P::S* __restric
     });
 }
 
+// The reverse: a state in the two-buffer form copied into form FORM.
+template <class M, class P, int FORM>
+__global__ __launch_bounds__(kBlock) void k_from_ab(const typename P::S* __restrict__ f,
+                                                    typename P::S* __restrict__ out, KParams k) {
+    const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= k.N) return;
+    const PopAt<M, kFormAB> src(k, c);
+    const PopAt<M, FORM> dst(k, c);
+    static_for<M::Q>([&](auto I) {
+        constexpr int i = decltype(I)::value;
+        out[dst.template at<i>()] = f[src.template at<i>()];
+    });
+}
+
 // Raw float64 sums of one cell: sum v, sum v e, sum v |e|^2 of the stored values.
 template <class M, int FORM, class S>
 __device__ __forceinline__ void cell_sums(const S* __restrict__ f, const KParams& k, long long c,
@@ -1161,6 +1175,21 @@ hipError_t launch_to_ab(ModelId m, Prec p, const KParams& kp, const void* f, voi
         using S = typename P::S;
         return with_form(kp, [&](auto F) {
             hipLaunchKernelGGL((k_to_ab<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                               dim3(kBlock), 0, s, static_cast<const S*>(f), static_cast<S*>(out),
+                               kp);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t launch_from_ab(ModelId m, Prec p, const KParams& kp, const void* f, void* out,
+                          hipStream_t s) {
+    return with_types(m, p, [&](auto M_, auto P_) {
+        using M = decltype(M_);
+        using P = decltype(P_);
+        using S = typename P::S;
+        return with_initial_form(kp, [&](auto F) {
+            hipLaunchKernelGGL((k_from_ab<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
                                dim3(kBlock), 0, s, static_cast<const S*>(f), static_cast<S*>(out),
                                kp);
             return hipGetLastError();

@@ -133,6 +133,12 @@ class Simulation:
         L.lbm_run_checkpointed(self.ctx, n, k, keep, ck, nb)
         return ck
 
+    def restore_checkpoint(self, n: int, k: int, ckpt: torch.Tensor, slot: int,
+                           keep: int = 1) -> None:
+        """Continue from snapshot `slot` of run_checkpointed(n, k, keep) (the
+        state at t = slot*k; slot = ceil(n/k): the final state)."""
+        L.lbm_restore_checkpoint(self.ctx, n, k, keep, ckpt, ckpt.numel() * 8, slot)
+
     def adjoint(self, n: int, k: int, ckpt: torch.Tensor, rho_init, U_init, T_init,
                 dL_drho_final, want_T: bool = True, want_omega: bool = True,
                 workspace: Optional[torch.Tensor] = None, keep: int = 1):

@@ -149,6 +149,7 @@ void check_create() {
     double cons[5];
     EXPECT(lbm_conservation(ctx, cons) == LBM_E_STATE);
     EXPECT(lbm_init_fields(ctx, nullptr, nullptr, nullptr) == LBM_E_STATE);
+    EXPECT(lbm_restore_checkpoint(ctx, 10, 3, 1, nullptr, 0, 0) == LBM_E_STATE);
     // host memory is not device memory (and there is no device here)
     std::vector<char> host(pop + 256);
     EXPECT(lbm_bind(ctx, host.data(), host.data() + 128, host.data()) != LBM_OK);

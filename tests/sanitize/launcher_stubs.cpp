@@ -23,6 +23,9 @@ hipError_t launch_step_aa(ModelId, Prec, const KParams&, void*, bool, void*, hip
 hipError_t launch_to_ab(ModelId, Prec, const KParams&, const void*, void*, hipStream_t) {
     return hipErrorNoDevice;
 }
+hipError_t launch_from_ab(ModelId, Prec, const KParams&, const void*, void*, hipStream_t) {
+    return hipErrorNoDevice;
+}
 hipError_t launch_moments(ModelId, Prec, const KParams&, const void*, double*, double*, double*,
                           hipStream_t) { return hipErrorNoDevice; }
 hipError_t launch_conservation(ModelId, Prec, const KParams&, const void*, double*, double*,
