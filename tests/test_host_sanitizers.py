@@ -1,7 +1,7 @@
 """The host code of the library (model tables, the Formula (5) solver, the
 model constructor and every argument check of the C ABI that runs without a
 device) built with AddressSanitizer, LeakSanitizer and UndefinedBehaviorSanitizer
-and exercised on valid and invalid input by tests/sanitize/abi_driver.cpp.
+and exercised on valid and invalid input by the checks in tests/sanitize/abi_checks.cpp.
 The device code is not part of this build: tests/sanitize/launcher_stubs.cpp
 stands in for the kernel launchers, which no call reaches without a GPU."""
 import os
@@ -19,9 +19,9 @@ def test_host_code_under_address_and_ub_sanitizers(tmp_path):
     gxx = shutil.which("g++")
     if gxx is None or not os.path.exists(os.path.join(ROCM, "lib", "libamdhip64.so")):
         pytest.skip("needs g++ and the HIP runtime library")
-    exe = str(tmp_path / "abi_driver")
+    exe = str(tmp_path / "abi_checks")
     srcs = [os.path.join(CSRC, "lbm_api.cpp"), os.path.join(CSRC, "lbm_model_host.cpp"),
-            os.path.join(ROOT, "tests", "sanitize", "abi_driver.cpp"),
+            os.path.join(ROOT, "tests", "sanitize", "abi_checks.cpp"),
             os.path.join(ROOT, "tests", "sanitize", "launcher_stubs.cpp")]
     cmd = [gxx, "-std=c++20", "-O1", "-g", "-fno-omit-frame-pointer",
            "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
