@@ -207,13 +207,15 @@ def run_tube(wname, precision, graph_steps=0, streaming="ab"):
     return out
 
 
-def run_fwd_adjoint(extent, omega, n, k, keep=1, streaming="ab"):
+def run_fwd_adjoint(extent, omega, n, k, keep=1, streaming="ab", accuracy=False):
     """Wall time of the checkpointed forward run and of the adjoint, same stream.
     `keep`: trailing segments whose step moments the forward run keeps;
-    `streaming`: "aa" runs the forward pass in place on one buffer."""
+    `streaming`: "aa" runs the forward pass in place on one buffer;
+    `accuracy`: also compare dL/domega and one directional derivative in T
+    with central differences of the FP64 forward run (outside the timing)."""
     import torch
     from paper_1303_4624_amd import Simulation
-    from synth_inputs import smooth_ic, target_theta
+    from synth_inputs import fd_direction, smooth_ic, target_theta
     rho, U, th = smooth_ic(extent)
     sim = Simulation("D3Q95", extent, omega, precision="fp32s", streaming=streaming)
     T = th * sim.T0
@@ -243,8 +245,28 @@ def run_fwd_adjoint(extent, omega, n, k, keep=1, streaming="ab"):
         t2 = time.perf_counter()
         res = {"fwd_ms": (t1 - t0) * 1e3, "bwd_ms": (t2 - t1) * 1e3,
                "plain_fwd_ms": t_plain * 1e3}
-        del ck, dT
+        del ck
     sim.close()
+    torch.cuda.empty_cache()
+    if accuracy:
+        # L = sum (rho_n - rho*)^2 of the FP64 forward run, central differences
+        s64 = Simulation("D3Q95", extent, omega, precision="fp64")
+
+        def loss(T_field, w):
+            s64.set_omega(w)
+            s64.init_fields(rho, U, T_field)
+            s64.step(n)
+            return float(((s64.moments()[0] - tgt) ** 2).sum())
+
+        h = 1e-6
+        fd_w = (loss(T, omega + h) - loss(T, omega - h)) / (2 * h)
+        d = fd_direction(extent, 0) * s64.T0
+        fd_t = (loss(T + h * d, omega) - loss(T - h * d, omega)) / (2 * h)
+        s64.close()
+        an_t = float((dT.double().cpu() * torch.as_tensor(d)).sum())
+        res["domega_rel_err_vs_fp64_fd"] = abs(dw - fd_w) / abs(fd_w)
+        res["dT_direction_rel_err_vs_fp64_fd"] = abs(an_t - fd_t) / abs(fd_t)
+    del dT
     torch.cuda.empty_cache()
     res["ratio_total_over_fwd"] = (res["fwd_ms"] + res["bwd_ms"]) / res["fwd_ms"]
     res["ratio_total_over_plain_fwd"] = (res["fwd_ms"] + res["bwd_ms"]) / res["plain_fwd_ms"]
@@ -427,7 +449,8 @@ def main():
         log("[bench] forward + adjoint on 128^3")
         # 128^3 fits many times over in HBM: keep the moments of every segment
         # (no recomputation); the minimum-memory variant keeps one segment.
-        out["fwd_adjoint_128c"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20, keep=10)
+        out["fwd_adjoint_128c"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20, keep=10,
+                                                  accuracy=True)
         out["fwd_adjoint_128c_min_memory"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20,
                                                              keep=1)
         out["fwd_adjoint_128c_in_place"] = run_fwd_adjoint((128, 128, 128), 1.4, 200, 20,
