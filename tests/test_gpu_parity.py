@@ -191,6 +191,39 @@ def test_errors_are_reported_not_faulted():
     sim.close()
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32s"])
+def test_non_finite_values_are_detected(precision):
+    # A NaN injected through the initial fields travels through the steps
+    # without any fault; the conservation sums and the omega gradient report
+    # it as LBM_E_NONFINITE.
+    from paper_1303_4624_amd import _lib as L
+    extent = (40, 12, 12)
+    rho, U, th = smooth_ic(extent, seeds=(61, 62, 63, 64, 65))
+    sim = new_sim("D3Q95", extent, 1.3, precision)
+    try:
+        bad = rho.copy()
+        bad[2, 3, 7] = np.nan
+        sim.init_fields(bad, U, th * sim.T0)
+        sim.step(1)
+        r = sim.moments()[0].cpu().numpy()
+        # one step carries it at most 5 cells along each axis (x is 40 wide)
+        assert np.isnan(r).any() and np.isfinite(r).any()
+        with pytest.raises(L.LBMError) as ex:
+            sim.conservation()
+        assert ex.value.status == L.LBM_E_NONFINITE
+        # the adjoint of a finite run with a NaN in dL/drho_n
+        sim.init_fields(rho, U, th * sim.T0)
+        ck = sim.run_checkpointed(4, 2)
+        g = np.zeros(rho.shape)
+        g[1, 1, 1] = np.nan
+        with pytest.raises(L.LBMError) as ex:
+            sim.adjoint(4, 2, ck, rho, U, th * sim.T0, g)
+        assert ex.value.status == L.LBM_E_NONFINITE
+        assert np.isfinite(sim.conservation()).all()     # the context is still usable
+    finally:
+        sim.close()
+
+
 def _patch(field, center, R):
     """Periodic (2R+1)^D patch of a grid-shaped field (axes ..., y, x) around
     center (x, y[, z])."""
