@@ -14,7 +14,8 @@
  * and the per-cell moments rho, U, T of the Maxwellian.  Around the update it
  * provides initialisation from macroscopic fields, moment output, global
  * conservation sums, the fixed end planes of the shock-tube experiment,
- * two-buffer or in-place (AA pattern) streaming, checkpointed runs, a
+ * two-buffer or in-place (AA pattern) streaming, checkpointed runs and
+ * resuming from their checkpoints, HIP-graph replay of step loops, a
  * hand-written adjoint that gives gradients of a loss on the final density
  * with respect to the initial temperature field and omega, and a general
  * constructor of on-lattice models (Formulas (5)-(10)).
