@@ -72,7 +72,7 @@ int reduce_blocks(long long N) {
 }
 
 long long step_blocks(ModelId, Prec, const KParams& kp) {
-    return static_cast<long long>(kp.ny) * kp.nz * kp.chunks;
+    return static_cast<long long>(kp.ny) * kp.nz / kp.rpb * kp.chunks;
 }
 
 }  // namespace lbm
@@ -168,6 +168,14 @@ void fill_kparams(lbm_ctx* ctx) {
     const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads(ctx->prec));
     k.chunks = rl.chunks;
     k.bx = rl.bx;
+    k.rpb = 1;
+    if (lbm::kPackRows && k.nx % 64 == 0) {
+        // whole rows per block: waves stay inside one row (nx % 64 = 0) and
+        // no block is partly empty (rpb divides the row count)
+        const int maxb = std::min(lbm::step_max_threads(ctx->prec), lbm::kPackMaxBlock);
+        while (k.nx * k.rpb * 2 <= maxb && rows % (k.rpb * 2) == 0) k.rpb *= 2;
+        if (k.rpb > 1) k.bx = k.nx * k.rpb;   // else: the row launch above (chunks >= 1)
+    }
     k.omega = ctx->omega;
     k.omc = 1.0 - ctx->omega;
     if (ctx->prec == Prec::F32S) k.omc = static_cast<double>(static_cast<float>(k.omc));
@@ -784,6 +792,19 @@ LBM_API int lbm_restore_checkpoint(lbm_ctx* ctx, int n, int k, int keep, const v
 
 namespace {
 
+// Launch parameters of the adjoint (its recomputation included): the
+// two-buffer form whatever scheme the forward run used, and packed-row
+// blocks of at most kPackAdjMaxBlock threads.
+KParams adjoint_params(const lbm_ctx* ctx) {
+    KParams k = ctx->kp;
+    k.form = lbm::kFormAB;
+    if (k.rpb > 1) {
+        while (k.rpb > 1 && k.nx * k.rpb > lbm::kPackAdjMaxBlock) k.rpb /= 2;
+        k.bx = k.nx * k.rpb;   // rows of nx = 64 j cells: one chunk per row
+    }
+    return k;
+}
+
 // Adjoint workspace: [three adjoint-state buffers][moments of one recomputed
 // segment][partials of A][partials of K(n)][partials of one invariant mark]
 // [A, K(n), one invariant mark per segment].
@@ -799,7 +820,7 @@ AdjLayout adj_layout(const lbm_ctx* ctx, int k, int segs, bool recompute) {
     L.pop = round_up(pop_bytes(ctx));
     L.mom_step = round_up(static_cast<size_t>(ctx->N) * (ctx->D + 2) * elem_bytes(ctx->prec));
     L.off_mom = 3 * L.pop;
-    L.nA = lbm::step_blocks(ctx->model, ctx->prec, ctx->kp);
+    L.nA = lbm::step_blocks(ctx->model, ctx->prec, adjoint_params(ctx));
     L.nK = (ctx->N + 255) / 256;
     L.off_partA = L.off_mom + (recompute ? static_cast<size_t>(k) * L.mom_step : 0);
     L.off_partK = L.off_partA + round_up(static_cast<size_t>(L.nA) * 8);
@@ -856,10 +877,7 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
         return fail(ctx, LBM_E_INVALID, "workspace must be 256-byte aligned");
     if ((rc = set_device(ctx)) != LBM_OK) return rc;
 
-    // The checkpoints and the adjoint's buffers are in the two-buffer form,
-    // whatever scheme the forward run used.
-    lbm::KParams kab = ctx->kp;
-    kab.form = lbm::kFormAB;
+    const lbm::KParams kab = adjoint_params(ctx);
     char* ws = static_cast<char*>(workspace);
     void* B[3] = {ws, ws + L.pop, ws + 2 * L.pop};
     char* mom = ws + L.off_mom;

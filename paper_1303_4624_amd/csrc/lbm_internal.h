@@ -52,6 +52,25 @@ constexpr int kRunAlign = LBM_RUN_ALIGN;
 constexpr int kRowGroup3DShift = LBM_ROW_GROUP_SHIFT;
 constexpr int kRowGroup3D = 1 << kRowGroup3DShift;
 
+// Whole grid rows per block of the row-blocked kernels when a row is a
+// multiple of 64 cells and several fit in one block (0: one row per block).
+#ifndef LBM_PACK_ROWS
+#define LBM_PACK_ROWS 1
+#endif
+constexpr bool kPackRows = LBM_PACK_ROWS != 0;
+// Largest block made of packed rows: forward steps, and the adjoint (whose
+// kernels hold more registers, so that large packed blocks leave fewer waves
+// per CU).  Measured on D3Q95 FP32-shifted 128^3: forward step +1.1 % with
+// 512 against one row per block; adjoint 2 % slower with 512, +0.3 % with 256.
+#ifndef LBM_PACK_MAXB
+#define LBM_PACK_MAXB 512
+#endif
+#ifndef LBM_PACK_ADJ_MAXB
+#define LBM_PACK_ADJ_MAXB 256
+#endif
+constexpr int kPackMaxBlock = LBM_PACK_MAXB;
+constexpr int kPackAdjMaxBlock = LBM_PACK_ADJ_MAXB;
+
 // A macroscopic state held fixed on boundary planes.
 struct FixedState {
     double rho;
@@ -71,6 +90,7 @@ struct KParams {
     int rg;                   // rows per group (consecutive y sharing interleaved runs), 1 or 2
     int rg_shift;             // log2(rg)
     int chunks;               // blocks per grid row (x direction)
+    int rpb;                  // grid rows per block (> 1 only with chunks = 1, nx % 64 = 0)
     int bx;                   // threads per block (multiple of 64)
     long long N;              // cells
     double omega;             // relaxation frequency

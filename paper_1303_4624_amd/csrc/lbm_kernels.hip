@@ -224,10 +224,19 @@ __device__ __forceinline__ Cell row_cell(const KParams& k) {
 #else
     const int b = blockIdx.x;
 #endif
-    const int chunk = b % k.chunks;
-    const int row = b / k.chunks;
+    int row, x;
+    if (kPackRows && k.rpb > 1) {
+        // rpb whole rows of nx (a multiple of 64) lanes: the row is uniform
+        // over each wave
+        const int sub = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x) / k.nx);
+        row = b * k.rpb + sub;
+        x = static_cast<int>(threadIdx.x) - sub * k.nx;
+    } else {
+        const int chunk = b % k.chunks;
+        row = b / k.chunks;
+        x = chunk * k.bx + static_cast<int>(threadIdx.x);
+    }
     Cell cl;
-    const int x = chunk * k.bx + static_cast<int>(threadIdx.x);
     cl.active = x < k.nx;
     cl.x = cl.active ? x : 0;
     cl.row = row;

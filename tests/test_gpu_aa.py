@@ -41,6 +41,8 @@ def _same(ab, aa):
     ("D2Q33", (70, 3)),
     ("D2Q33", (33, 17)),
     ("D2Q33", (2, 1)),
+    ("D3Q95", (64, 6, 4)),      # whole rows per block
+    ("D2Q33", (128, 6)),
 ])
 @pytest.mark.parametrize("precision", ["fp64", "fp32s"])
 def test_in_place_equals_two_buffer_bitwise(model, extent, precision):

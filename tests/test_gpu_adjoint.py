@@ -42,7 +42,9 @@ def _loss_gpu(sim, rho, U, T, n, tgt):
                                               ("D2Q33", (20, 12), 40, 9),
                                               # two single-step segments; ragged tiny grids
                                               ("D3Q95", (7, 5, 4), 2, 1),
-                                              ("D2Q33", (9, 6), 3, 2)])
+                                              ("D2Q33", (9, 6), 3, 2),
+                                              # whole rows per block
+                                              ("D3Q95", (64, 4, 4), 5, 2)])
 @pytest.mark.parametrize("precision,tol,tol_w", [("fp64", 1e-9, 1e-9), ("fp32s", 1e-5, 2e-4)])
 def test_adjoint_matches_oracle_autograd(model, extent, n, k, precision, tol, tol_w):
     # dL/domega = sum_t (A^t - K(t+1)) / (1 - omega) cancels: with K taken as

@@ -37,6 +37,8 @@ def test_fp64_riemann_workloads_match_oracle(wname):
     ("D3Q95", (1, 1, 1), 3),        # every displacement wraps onto the cell itself
     ("D2Q33", (70, 3), 15),
     ("D2Q33", (2, 1), 4),
+    ("D3Q95", (64, 6, 4), 6),       # rows of 64 cells: four whole rows per block
+    ("D2Q33", (64, 12), 6),
 ])
 def test_fp64_small_and_ragged_grids_match_oracle(model, extent, steps):
     _say("case", model, extent, steps)

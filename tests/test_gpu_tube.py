@@ -55,6 +55,7 @@ def _oracle(model, rho, U, th, steps, omega, hold):
     ("D3Q95", (300, 2, 24), 10, 0, 5),   # one held end; rows span two chunks, ragged tail
     ("D2Q33", (7, 33), 30, 4, 4),
     ("D2Q33", (5, 28), 20, 3, 0),
+    ("D3Q95", (64, 2, 24), 10, 5, 5),    # whole rows per block: held and free rows in one block
 ])
 def test_held_tube_matches_oracle_elementwise(model, extent, steps, n_lo, n_hi):
     _say("case", model, extent, steps, n_lo, n_hi)
