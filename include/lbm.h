@@ -286,8 +286,9 @@ int lbm_conservation(lbm_ctx* ctx, double* out);
  * lattice.  Returns LBM_E_INVALID for n_lo, n_hi < 0, n_lo + n_hi >
  * extent[D-1], NULL or non-positive states, LBM_E_NONFINITE for NaN/Inf.
  * Works with both streaming schemes.
- * lbm_run_checkpointed and lbm_adjoint return LBM_E_UNSUPPORTED while
- * planes are held.
+ * lbm_run_checkpointed works with held planes, and so does the temperature
+ * gradient of lbm_adjoint (see there); its omega gradient needs an
+ * all-periodic lattice.
  */
 int lbm_set_fixed_planes(lbm_ctx* ctx, int n_lo, int n_hi, const double* state_lo,
                          const double* state_hi);
@@ -387,6 +388,12 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int n, int k, int keep, size
  *   dL_domega          : host double out (may be NULL); when requested,
  *                        |1 - omega| >= 1e-3 is required (LBM_E_INVALID
  *                        otherwise) and the call synchronises the stream.
+ * With held planes (lbm_set_fixed_planes, set as in the forward run) the
+ * post-collision values of held cells are constants: their adjoint state is
+ * zero at every t <= n, and the initial field on the held planes still
+ * counts through the first step.  The omega gradient, which relies on the
+ * homogeneity of the all-periodic step, is then refused (LBM_E_UNSUPPORTED);
+ * request dL_dT_init alone.
  * The context's populations are left as they were.
  */
 int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt, size_t ckpt_bytes,

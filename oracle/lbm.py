@@ -108,21 +108,22 @@ def density_loss(rho_final: torch.Tensor, rho_target: torch.Tensor) -> torch.Ten
     return ((rho_final - rho_target) ** 2).sum()
 
 
-def forward_density(vs: VelocitySet, rho0, U0, T_init: torch.Tensor, omega, n: int) -> torch.Tensor:
+def forward_density(vs: VelocitySet, rho0, U0, T_init: torch.Tensor, omega, n: int,
+                    hold=None) -> torch.Tensor:
     f = feq(vs, to_tensor(rho0), to_tensor(U0), T_init)
-    f = run(vs, f, omega, n)
+    f = run(vs, f, omega, n, hold)
     return f.sum(0)
 
 
 def loss_and_grad(vs: VelocitySet, rho0, U0, T_init, omega: float, n: int,
-                  rho_target) -> Tuple[float, torch.Tensor, float]:
+                  rho_target, hold=None) -> Tuple[float, torch.Tensor, float]:
     """Loss and its gradient with respect to the initial temperature field and
     omega, by float64 reverse-mode automatic differentiation through the
     initial equilibrium and n update steps (independent of any hand-written
-    adjoint)."""
+    adjoint); `hold` as for step (end planes reset to a fixed equilibrium)."""
     T = to_tensor(T_init).clone().requires_grad_(True)
     w = torch.tensor(float(omega), dtype=torch.float64, requires_grad=True)
-    rho_n = forward_density(vs, rho0, U0, T, w, n)
+    rho_n = forward_density(vs, rho0, U0, T, w, n, hold)
     L = density_loss(rho_n, to_tensor(rho_target))
     L.backward()
     return float(L.detach()), T.grad.detach(), float(w.grad)

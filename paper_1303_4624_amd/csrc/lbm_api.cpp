@@ -709,9 +709,6 @@ LBM_API int lbm_run_checkpointed(lbm_ctx* ctx, int n, int k, int keep, void* ckp
     int rc;
     if ((rc = require_init(ctx)) != LBM_OK) return rc;
     if (n < 1 || k < 1 || keep < 1) return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
-    if (ctx->hold_lo + ctx->hold_hi > 0)
-        return fail(ctx, LBM_E_UNSUPPORTED, "checkpointed runs need an all-periodic lattice "
-                                            "(fixed planes are set)");
     const CkLayout c = ck_layout(ctx, n, k, keep);
     if (ckpt_bytes < c.total) return fail(ctx, LBM_E_INVALID, "checkpoint buffer too small");
     if ((rc = check_dev(ctx, ckpt, c.total, "ckpt")) != LBM_OK) return rc;
@@ -852,9 +849,10 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
     if (!ctx->bound) return fail(ctx, LBM_E_STATE, "no buffers bound (call lbm_bind)");
     if (n < 1 || k < 1 || keep < 1)
         return fail(ctx, LBM_E_INVALID, "need n >= 1, k >= 1, keep >= 1");
-    if (ctx->hold_lo + ctx->hold_hi > 0)
-        return fail(ctx, LBM_E_UNSUPPORTED, "the adjoint needs an all-periodic lattice "
-                                            "(fixed planes are set)");
+    if (dL_domega && ctx->hold_lo + ctx->hold_hi > 0)
+        return fail(ctx, LBM_E_UNSUPPORTED, "the omega gradient needs an all-periodic lattice "
+                                            "(fixed planes are set); the temperature gradient "
+                                            "does not");
     if (dL_domega && std::fabs(1.0 - ctx->omega) < 1e-3)
         return fail(ctx, LBM_E_INVALID,
                     "the omega gradient needs |1 - omega| >= 1e-3 (it is divided by 1 - omega)");

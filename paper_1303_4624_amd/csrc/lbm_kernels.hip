@@ -541,6 +541,20 @@ __device__ __forceinline__ Macro relax_cell(const KParams& k, const typename P::
 // HOLD: rows inside the held planes of the slowest axis (the fixed end
 // planes of the shock tube) store f^eq of the held state instead; the test
 // is uniform over a block.
+// The stored step moments of a cell on a held plane: those of the held state.
+template <class M, class P>
+__device__ __forceinline__ void store_held_moments(const KParams& k, const Cell& cl,
+                                                   const FixedState& st,
+                                                   typename P::S* __restrict__ mom) {
+    using S = typename P::S;
+    if (!cl.active) return;
+    mom[cl.c] = S(P::shifted ? st.rho - k.rho0 : st.rho);
+    mom[k.N + cl.c] = S(st.U[0]);
+    mom[2 * k.N + cl.c] = S(st.U[1]);
+    if constexpr (M::D == 3) mom[3 * k.N + cl.c] = S(st.U[2]);
+    mom[(M::D + 1) * k.N + cl.c] = S(st.T * k.invT0 - 1.0);
+}
+
 template <class M, class P, bool STORE_MOM, bool HOLD>
 __global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
 void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst, KParams k,
@@ -557,6 +571,7 @@ void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ d
             PlaneWriter<S> out_w(dst, k, cl, M::Q);
             feq_cell<M, P>(k, st.rho, st.U[0], st.U[1], st.U[2], st.T,
                            [&](auto, S val) { out_w.put(val); });
+            if constexpr (STORE_MOM) store_held_moments<M, P>(k, cl, st, mom);
             return;
         }
     }
@@ -617,6 +632,7 @@ void k_step_aa(typename P::S* f, KParams k, typename P::S* __restrict__ mom) {
         if (sl < k.hold_lo || sl >= L - k.hold_hi) {
             const FixedState& st = (sl < k.hold_lo) ? k.hold[0] : k.hold[1];
             feq_cell<M, P>(k, st.rho, st.U[0], st.U[1], st.U[2], st.T, put);
+            if constexpr (STORE_MOM) store_held_moments<M, P>(k, cl, st, mom);
             return;
         }
     }
@@ -812,6 +828,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restric
 // Adjoint.
 //
 // lambda^n_i(x) = dL/drho_n(x) for every i; partK[block] = sum dL/drho_n * rho_n.
+// On held planes rho_n is the held state's, a constant: lambda^n = 0 there.
 template <class M, class P>
 __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __restrict__ fn,
                                                         const double* __restrict__ dLdrho,
@@ -821,7 +838,11 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     const long long c = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     double acc[1] = {0.0};
     if (c < k.N) {
-        const double g = dLdrho[c];
+        const long long plane = static_cast<long long>(k.nx) * (M::D == 3 ? k.ny : 1);
+        const long long sl = c / plane;
+        const long long L = (M::D == 3) ? k.nz : k.ny;
+        const bool held = sl < k.hold_lo || sl >= L - k.hold_hi;
+        const double g = held ? 0.0 : dLdrho[c];
         double m0 = 0.0;
         const PopAt<M, kFormAB> pa(k, c);
         static_for<M::Q>([&](auto I) {
@@ -868,7 +889,10 @@ __device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, do
 // The MARK instances (one step per checkpoint segment) hold the mark's loads
 // as well and are allowed twice the registers (2 waves per SIMD) to avoid
 // spilling.
-template <class M, class P, bool COLLIDE, bool MARK>
+// HOLD: the post-collision values of cells on held planes are constants, so
+// their adjoint state is zero (the cells are computed like the others and
+// their output replaced, keeping every wave on the same barriers).
+template <class M, class P, bool COLLIDE, bool MARK, bool HOLD>
 __global__ __launch_bounds__(P::max_block)
 __attribute__((amdgpu_waves_per_eu(MARK ? (P::adj_waves < 2 ? P::adj_waves : 2) : P::adj_waves)))
 void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict__ ldst,
@@ -992,6 +1016,12 @@ void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict
     const R gr = R(w * grho);
     const R omc = R(k.omc);
     PlaneWriter<S> out_w(ldst, k, cl, Q);
+    bool held = false;
+    if constexpr (HOLD) {
+        const int sl = (D == 3) ? cl.z : cl.y;
+        const int L = (D == 3) ? k.nz : k.ny;
+        held = sl < k.hold_lo || sl >= L - k.hold_hi;
+    }
 
     static_for<Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
@@ -1002,7 +1032,9 @@ void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict
         if constexpr (ex != 0) hv = fma(R(ex), gjx, hv);
         if constexpr (ey != 0) hv = fma(R(ey), gjy, hv);
         if constexpr (ez != 0) hv = fma(R(ez), gjz, hv);
-        out_w.put(fma(omc, mu[i], hv));
+        const S out = fma(omc, mu[i], hv);
+        if constexpr (HOLD) out_w.put(held ? S(0) : out);
+        else out_w.put(out);
     });
 
     if constexpr (MARK) {
@@ -1012,7 +1044,7 @@ void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict
             else partM[blockIdx.x] = v;
         });
     } else {
-        double acc[1] = {cl.active ? rho * s0 : 0.0};
+        double acc[1] = {(cl.active && !held) ? rho * s0 : 0.0};
         block_sum<1>(acc, partA + blockIdx.x, true);
     }
 }
@@ -1134,7 +1166,11 @@ hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, vo
         using P = decltype(P_);
         using S = typename P::S;
         const dim3 grid(static_cast<unsigned>(blocks));
-        if (mom_out) {
+        if (mom_out && kp.hold_lo + kp.hold_hi > 0) {
+            hipLaunchKernelGGL((k_step<M, P, true, true>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
+                               static_cast<const S*>(src), static_cast<S*>(dst), kp,
+                               static_cast<S*>(mom_out));
+        } else if (mom_out) {
             hipLaunchKernelGGL((k_step<M, P, true, false>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
                                static_cast<const S*>(src), static_cast<S*>(dst), kp,
                                static_cast<S*>(mom_out));
@@ -1164,11 +1200,13 @@ hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool pu
         };
         const bool hold = kp.hold_lo + kp.hold_hi > 0;
         if (push) {
-            if (mom_out) go(k_step_aa<M, P, true, false, true>);
+            if (mom_out && hold) go(k_step_aa<M, P, true, true, true>);
+            else if (mom_out) go(k_step_aa<M, P, true, false, true>);
             else if (hold) go(k_step_aa<M, P, true, true, false>);
             else go(k_step_aa<M, P, true, false, false>);
         } else {
-            if (mom_out) go(k_step_aa<M, P, false, false, true>);
+            if (mom_out && hold) go(k_step_aa<M, P, false, true, true>);
+            else if (mom_out) go(k_step_aa<M, P, false, false, true>);
             else if (hold) go(k_step_aa<M, P, false, true, false>);
             else go(k_step_aa<M, P, false, false, false>);
         }
@@ -1275,12 +1313,15 @@ hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void*
                                static_cast<const S*>(mom), kp, partA,
                                static_cast<const S*>(mark_state), partM);
         };
+        const bool hold = kp.hold_lo + kp.hold_hi > 0;
         if (mom) {
-            if (mark_state) go(k_adjoint<M, P, true, true>);
-            else go(k_adjoint<M, P, true, false>);
+            // (the omega marks are not taken with held planes)
+            if (hold) go(k_adjoint<M, P, true, false, true>);
+            else if (mark_state) go(k_adjoint<M, P, true, true, false>);
+            else go(k_adjoint<M, P, true, false, false>);
         } else {
-            if (mark_state) go(k_adjoint<M, P, false, true>);
-            else go(k_adjoint<M, P, false, false>);
+            if (mark_state) go(k_adjoint<M, P, false, true, false>);
+            else go(k_adjoint<M, P, false, false, false>);
         }
         return hipGetLastError();
     });

@@ -211,6 +211,41 @@ def test_autograd_gradient_matches_central_differences():
     assert abs(fdw - gw) <= 1e-6 * abs(gw)
 
 
+def test_autograd_gradient_with_held_planes_matches_central_differences():
+    # The tube's end planes: the held values are constants, so the gradient
+    # with respect to T_init comes only through the first step's gathers from
+    # them and through the free cells; central differences of the forward run
+    # (no autograd) check it, and T_init on a held plane after the first step
+    # matters only through that first step.
+    v = vs.velocity_set("D2Q33")
+    ext = (5, 14)
+    rho, U, th = tube_ic(ext, 7, (2.0, 1.0), (1.0, 1.1))
+    pr, pU, pth = smooth_ic(ext, seeds=(41, 42, 43, 44), amp_u=0.02, amp_rho=0.02,
+                            amp_theta=0.02)
+    rho, U, th = rho * pr, U + pU, th * pth
+    T = th * v.T0
+    hold = (4, 4, (2.0, 0.0, 0.0, v.T0), (1.0, 0.0, 0.0, 1.1 * v.T0))
+    target = 1.2 + 0.01 * np.cos(np.arange(70).reshape(14, 5))
+    L, gT, gw = lbm.loss_and_grad(v, rho, U, T, 1.3, 5, target, hold)
+    eps = 1e-6 * v.T0
+
+    def loss(Tf):
+        with torch.no_grad():
+            r = lbm.forward_density(v, rho, U, torch.as_tensor(Tf), 1.3, 5, hold)
+            return float(lbm.density_loss(r, torch.as_tensor(target)))
+
+    rng = np.random.default_rng(1)
+    d = rng.standard_normal(T.shape)
+    fd = (loss(T + eps * d) - loss(T - eps * d)) / (2 * eps)
+    an = float((gT.numpy() * d).sum())
+    assert abs(fd - an) <= 1e-6 * abs(an)
+    # a held-plane cell: nonzero (its initial value feeds the first step)
+    e = np.zeros(T.shape)
+    e[1, 2] = 1.0
+    fd1 = (loss(T + eps * e) - loss(T - eps * e)) / (2 * eps)
+    assert abs(fd1 - float(gT[1, 2])) <= 1e-6 * abs(fd1) and abs(fd1) > 0
+
+
 def test_adjoint_pairing_is_invariant_in_time():
     # The step f -> S C(f) is homogeneous of degree one (U and T are ratios of
     # moments), so <dL/df^t, f^t> is the same at every t.
