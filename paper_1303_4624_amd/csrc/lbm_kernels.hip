@@ -4,7 +4,7 @@
 // Data layout: row-blocked.  The Q populations of a group of consecutive
 // grid rows are contiguous, population-major (see PopAt / row_base), cells
 // x-fastest.  One thread owns one cell and a block one grid row (or a chunk
-// of it).  Every population read is a contiguous run of a source row
+// of it, or several whole rows of 64j cells).  Every population read is a contiguous run of a source row
 // (neighbouring threads read neighbouring x), so the gather f_i(x - e_i) is
 // coalesced; the x-wrap of the periodic grid is folded into a per-lane
 // offset, the y/z-wrap into wave-uniform slab bases and row offsets.
@@ -887,8 +887,8 @@ __device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, do
 // B the stored state the forward run streamed into f^{t+1} (a checkpoint),
 // i.e. the invariant <lambda^{t+1}, f^{t+1}> of the step's homogeneity.
 // The MARK instances (one step per checkpoint segment) hold the mark's loads
-// as well and are allowed twice the registers (2 waves per SIMD) to avoid
-// spilling.
+// as well and may use up to 256 registers (2 waves per SIMD instead of 3) to
+// avoid spilling.
 // HOLD: the post-collision values of cells on held planes are constants, so
 // their adjoint state is zero (the cells are computed like the others and
 // their output replaced, keeping every wave on the same barriers).
