@@ -1,7 +1,8 @@
 """Graph replay of lbm_step: bit-identical to launching the steps one by one,
 checked after every call, with eager work and synchronisation between the
 replays, across step counts that are and are not multiples of the graph,
-an omega change, in-place streaming and held planes."""
+an omega change, in-place streaming, held planes, and checkpointed runs and
+restores in between."""
 import numpy as np
 import pytest
 import torch
@@ -74,6 +75,33 @@ def test_graph_replay_with_held_planes(streaming):
                 plain.step(n)
                 graph.step(n)
                 _check(plain, graph)
+        finally:
+            plain.close()
+            graph.close()
+
+
+@pytest.mark.parametrize("streaming", ["ab", "aa"])
+def test_graph_replay_around_checkpointed_runs_and_restores(streaming):
+    # Checkpointed runs and restores change the buffer parity or storage
+    # form under a captured graph; the replays that follow must still equal
+    # single launches.
+    extent = (20, 6, 8)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        rho, U, th = smooth_ic(extent, seeds=(71, 72, 73, 74, 75), amp_u=0.03)
+        plain, graph = _pair("D3Q95", extent, "fp32s", streaming, stream)
+        try:
+            cks = []
+            for s in (plain, graph):
+                s.init_fields(rho, U, th * s.T0)
+                s.step(8)
+                cks.append(s.run_checkpointed(7, 3))
+                s.step(9)
+            _check(plain, graph)
+            for s, ck in zip((plain, graph), cks):
+                s.restore_checkpoint(7, 3, ck, 1)
+                s.step(12)
+            _check(plain, graph)
         finally:
             plain.close()
             graph.close()
