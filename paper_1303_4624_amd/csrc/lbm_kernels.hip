@@ -304,14 +304,47 @@ __device__ __forceinline__ void store_pop(char* p, S val) {
 }
 
 // Gather v_i = src_i(x - SIGN*e_i) with periodic wrap on every axis.
+// Order in which a gather issues its loads: the velocity order, or sorted
+// by source slab, then source row (LBM_ADJ_GATHER_SORTED, transposed gather).
+// Measured: the adjoint on D3Q95 FP32-shifted 128^3 1.3 % faster sorted; the
+// forward pull sorted lost 0.5 % at 384^3 (and gained 1.5 % at 256^3), so it
+// keeps the velocity order.  The order changes no value, only the issue order.
+#ifndef LBM_ADJ_GATHER_SORTED
+#define LBM_ADJ_GATHER_SORTED 1
+#endif
+template <class M, bool SORTED>
+struct LoadOrder {
+    struct Arr {
+        int v[M::Q];
+    };
+    static constexpr Arr make() {
+        Arr o{};
+        for (int i = 0; i < M::Q; ++i) o.v[i] = i;
+        if (SORTED) {
+            const auto key = [](int i) {
+                return (M::table.e[i][2] * 16 + M::table.e[i][1]) * 16 + M::table.e[i][0];
+            };
+            for (int a = 1; a < M::Q; ++a)
+                for (int b = a; b > 0 && key(o.v[b]) < key(o.v[b - 1]); --b) {
+                    const int t = o.v[b];
+                    o.v[b] = o.v[b - 1];
+                    o.v[b - 1] = t;
+                }
+        }
+        return o;
+    }
+    static constexpr Arr order = make();
+};
+
 // SIGN = +1 is the pull of the forward update, SIGN = -1 the transposed
 // (adjoint) streaming.
 template <class M, int SIGN, class S>
 __device__ __forceinline__ void gather(const S* __restrict__ src, const KParams& k, const Cell& cl,
                                        S (&v)[M::Q]) {
     const SlabAddr<M, S, const char> ad(reinterpret_cast<const char*>(src), k, cl);
+    constexpr bool sorted = SIGN < 0 && LBM_ADJ_GATHER_SORTED != 0;
     static_for<M::Q>([&](auto I) {
-        constexpr int i = decltype(I)::value;
+        constexpr int i = LoadOrder<M, sorted>::order.v[decltype(I)::value];
         constexpr int ex = SIGN * M::table.e[i][0];
         constexpr int ey = SIGN * M::table.e[i][1];
         constexpr int ez = SIGN * M::table.e[i][2];
