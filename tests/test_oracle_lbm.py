@@ -260,8 +260,14 @@ def test_adjoint_pairing_is_invariant_in_time():
     L = lbm.density_loss(fs[-1].sum(0), target)
     L.backward()
     pairs = [float((f.grad * f.detach()).sum()) for f in fs]
+    # The pairing is a sum whose terms cancel about 1e5-fold (here
+    # |pair| ~ 1.1e-5 against sum |terms| ~ 1.1), so its float64 rounding
+    # scales with sum |terms|, not with |pair|: measured 1.2e-17 * sum |terms|.
+    # A step that is not homogeneous moves the pairing by O(|pair|), i.e.
+    # 1e-5 * sum |terms|, ten orders above this bar.
     scale = max(float((f.grad * f.detach()).abs().sum()) for f in fs)
-    assert max(abs(p - pairs[-1]) for p in pairs) <= 1e-13 * scale
+    assert abs(pairs[-1]) > 1e-7 * scale
+    assert max(abs(p - pairs[-1]) for p in pairs) <= 1e-15 * scale
 
 
 # -- the shock tube with end planes held at C_L and C_R (results section) ----
