@@ -30,7 +30,9 @@ sys.path.insert(0, ROOT)
 METRIC = "D3Q95 MLUPS & HBM GB/s vs roofline (FP32-shifted vs FP64; fwd+adjoint)"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stream_collide_d3q95_fp32s_384c_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_1303_4624_amd", "csrc", "lbm_kernels.hip")
+# The sources the headline kernel (k_step, D3Q95 FP32-shifted) is built from.
+KERNEL_SRCS = [os.path.join(ROOT, "paper_1303_4624_amd", "csrc", f) for f in (
+    "lbm_kernels.h", "lbm_kernels_d3q95_f32s.hip", "lbm_internal.h", "lbm_model.h")]
 
 
 def log(*a):
@@ -38,8 +40,11 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -344,6 +349,10 @@ def cpu_oracle_adjoint_baseline(extent=(32, 32, 32), steps=12):
                       f"sum (rho_n - rho*)^2 w.r.t. T_init and omega ({dt:.1f} s)"}
 
 
+# Side measurements after the headline (all by default; --only picks some).
+SECTIONS = ("copy", "256c", "d2q33", "aa", "tubes", "adjoint")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -354,7 +363,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 2 GiB device copy first (reference dispatch for HBM counters)")
+    ap.add_argument("--only", default="",
+                    help="comma-separated side measurements to run (default: all of them): "
+                         + ",".join(SECTIONS))
     args = ap.parse_args()
+    only = set(x for x in args.only.split(",") if x)
+    if only - set(SECTIONS):
+        ap.error(f"unknown sections {sorted(only - set(SECTIONS))}")
+    want = (lambda name: not only or name in only)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "slab decomposition is a design, not part of this build.", file=sys.stderr)
@@ -417,10 +433,11 @@ def main():
         "finite": ok,
         "mass_after": cons[0],
     }
-    if not args.no_extras:
+    if not args.no_extras and want("copy"):
         cbw = copy_bandwidth()
         out["roofline"]["copy_GBs"] = round(cbw, 1)
         out["roofline"]["frac_of_copy"] = round(achieved / cbw, 4)
+    if not args.no_extras and want("256c"):
         log("[bench] fp64 vs fp32s on 256^3")
         thr, errs = run_fp64_and_error((256, 256, 256), 1.5, 100, 200, steps_err_long=1000)
         err = errs[0]
@@ -430,6 +447,7 @@ def main():
         out["fp64_256c"]["roofline_frac"] = round(
             out["fp64_256c"]["mlups"] * 1520 / 1e3 / HBM_PEAK_GBS, 4)
         out["fp32s_vs_fp64_256c"] = err
+    if not args.no_extras and want("d2q33"):
         log("[bench] D2Q33 fp64 vs fp32s on 8192^2")
         thr, err = run_fp64_and_error((8192, 8192), 1.5, 100, 200, model="D2Q33")
         for prec, bpc in (("fp64", 528), ("fp32s", 264)):
@@ -437,15 +455,18 @@ def main():
             d["roofline_frac"] = round(d["mlups"] * bpc / 1e3 / HBM_PEAK_GBS, 4)
             out[f"d2q33_{prec}_8192sq"] = d
         out["d2q33_fp32s_vs_fp64_8192sq"] = err
+    if not args.no_extras and want("aa"):
         log("[bench] in-place (AA) streaming, 384^3 and 768^3")
         out["aa_fp32s_384c"] = run_aa((384, 384, 384), 100)
         out["aa_fp32s_768c"] = run_aa((768, 768, 768), 30, tile=(192, 192, 192))
+    if not args.no_extras and want("tubes"):
         log("[bench] shock tubes with held end planes")
         for wname in ("d3q95_11x11x800_tube", "d2q33_11x800_tube"):
             for prec in ("fp64", "fp32s"):
                 out[f"{wname}_{prec}"] = run_tube(wname, prec)
                 out[f"{wname}_{prec}_graph"] = run_tube(wname, prec, graph_steps=40)
             out[f"{wname}_fp32s_aa"] = run_tube(wname, "fp32s", streaming="aa")
+    if not args.no_extras and want("adjoint"):
         log("[bench] forward + adjoint on 128^3")
         # 128^3 fits many times over in HBM: keep the moments of every segment
         # (no recomputation); the minimum-memory variant keeps one segment.

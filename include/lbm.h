@@ -3,14 +3,17 @@
  *
  * The library runs the lattice Boltzmann update of Shim's on-lattice
  * higher-order thermal models (the 2D 33-velocity model of Table 2 and the 3D
- * 95-velocity model of Table 3):
+ * 95-velocity model of Table 3, both of order m = 4, and the lower-order 3D
+ * 19- and 15-velocity sets of order m = 2 that the paragraph after
+ * Formula (10) says the same construction gives):
  *
  *     f_i(x + e_i, t + 1) = (1 - omega) f_i(x, t) + omega f_i^eq(x, t)
  *
  * on a periodic grid (the update rule of the method; lattice units, dx = dt = 1,
- * particle displacement e_i per step), with the 4th-order Hermite equilibrium
- * f_i^eq = w_i rho P^(4)(v_i) (the polynomial-equilibrium form next to
- * Formula (2), order N = m = 4 as the paragraph after Formula (8) requires),
+ * particle displacement e_i per step), with the Hermite equilibrium
+ * f_i^eq = w_i rho P^(N)(v_i) of order N = m (the polynomial-equilibrium form
+ * next to Formula (2); N >= m as the paragraph after Formula (5) requires:
+ * N = 4 for the models of Tables 2 and 3, N = 2 for the lower-order sets),
  * and the per-cell moments rho, U, T of the Maxwellian.  Around the update it
  * provides initialisation from macroscopic fields, moment output, global
  * conservation sums, the fixed end planes of the shock-tube experiment,
@@ -100,17 +103,21 @@ typedef enum lbm_precision {
  * lbm_velocity_set - the canonical velocity set of a supported model and its
  * weights, solved on the host.
  *
- * Builds the union of the symmetry groups of Table 2 (D = 2, Q = 33) or
- * Table 3 (D = 3, Q = 95): each group is the orbit of its representative
- * under coordinate permutations and sign changes (the group construction
- * before Formula (9)).  Canonical order: groups in table order, vectors of a
- * group sorted ascending as integer tuples.  Then solves the square system of
- * Formula (5) (even moments up to n_max = 2m = 8, Omega(4, D) equations,
- * Formula (10) unknowns: one weight per group plus c) by Newton's method in
- * binary128, started from the printed table values, and rounds the root to
- * float64.  The right-hand side is normalised so that the weights sum to one.
+ * Builds the union of the symmetry groups of Table 2 (D = 2, Q = 33),
+ * Table 3 (D = 3, Q = 95) or of a lower-order 3D set (Q = 19: the groups of
+ * (0,0,0), (1,0,0), (1,1,0); Q = 15: (0,0,0), (1,0,0), (1,1,1)): each group
+ * is the orbit of its representative under coordinate permutations and sign
+ * changes (the group construction before Formula (9)).  Canonical order:
+ * groups in that order, vectors of a group sorted ascending as integer
+ * tuples.  Then solves the square system of Formula (5) (even moments up to
+ * n_max = 2m: m = 4 for Tables 2 and 3, Omega(4, D) equations; m = 2 for the
+ * lower-order sets, Omega(2, 3) = 4 equations; Formula (10) unknowns: one
+ * weight per group plus c) by Newton's method in binary128, started from the
+ * printed table values (the lower-order sets: least-squares weights at
+ * c = 1), and rounds the root to float64.  The right-hand side is
+ * normalised so that the weights sum to one.
  *
- *   D, Q  : 2 and 33, or 3 and 95; otherwise LBM_E_UNSUPPORTED.
+ *   D, Q  : 2 and 33, or 3 and 95, 19 or 15; otherwise LBM_E_UNSUPPORTED.
  *   e     : host int32[Q][D] out, displacements (may be NULL).
  *   w     : host double[Q] out, weight of each velocity (may be NULL).
  *   c     : host double out, the speed of Formula (5) (may be NULL).
@@ -146,8 +153,10 @@ int lbm_equation_count(int m, int D, int* count);
  * of Table 2 or 3 the result equals lbm_velocity_set bit for bit.
  * Returns LBM_E_UNSUPPORTED for other D, LBM_E_INVALID for a system that is
  * not square, repeated groups, no convergence, a non-positive weight or c,
- * or q_cap < Q (Q is still reported in the last case).  Only the D2Q33 and
- * D3Q95 models have kernels (lbm_create).
+ * or q_cap < Q (Q is still reported in the last case).  The sets with
+ * kernels are those of lbm_velocity_set (lbm_create): built here from the
+ * same representatives (and m = 2 for the lower-order 3D sets) they are
+ * accepted by lbm_create.
  */
 int lbm_model_build(int D, int m, int G, const int32_t* reps, const double* w_guess,
                     double c_guess, int q_cap, int32_t* e, int32_t* group, double* w, double* c,
@@ -160,11 +169,13 @@ int lbm_model_build(int D, int m, int G, const int32_t* reps, const double* w_gu
  *               released by lbm_destroy).
  *   D, Q, e   : dimension, velocity count and host int32[Q][D]
  *               displacements; must equal a supported model in canonical
- *               order (see lbm_velocity_set), else LBM_E_UNSUPPORTED.
+ *               order (see lbm_velocity_set: D2Q33, D3Q95, D3Q19, D3Q15),
+ *               else LBM_E_UNSUPPORTED.
  *   w         : host double[Q] weights: positive, equal within each group,
  *               summing to 1 within 1e-12.
- *   c         : speed of the model; Formula (5) must hold at (w, c) with
- *               residual <= 1e-10, else LBM_E_INVALID.
+ *   c         : speed of the model; Formula (5) (up to n_max = 2m of the
+ *               model) must hold at (w, c) with residual <= 1e-10, else
+ *               LBM_E_INVALID.
  *   extent    : host int64[D] = {nx, ny[, nz]}, each >= 1 and <= 2^24,
  *               N < 2^31 cells (more than 288 GB of populations); the
  *               populations of one slab of the slowest axis (nx*ny*Q
@@ -388,6 +399,13 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int n, int k, int keep, size
  *   dL_domega          : host double out (may be NULL); when requested,
  *                        |1 - omega| >= 1e-3 is required (LBM_E_INVALID
  *                        otherwise) and the call synchronises the stream.
+ *                        Accuracy: A - K nearly cancels and is divided by
+ *                        1 - omega, so the LBM_FP32_SHIFTED error grows like
+ *                        1/|1 - omega| (measured against central differences
+ *                        of the float64 run, D3Q95 48x40x32, 60 steps:
+ *                        3.4e-5 at omega = 0.9, 4.4e-4 at omega = 1.05; 128^3,
+ *                        200 steps: 7e-6 at omega = 1.4).  LBM_FP64 stays near
+ *                        1e-12 relative.
  * With held planes (lbm_set_fixed_planes, set as in the forward run) the
  * post-collision values of held cells are constants: their adjoint state is
  * zero at every t <= n, and the initial field on the held planes still

@@ -1,6 +1,7 @@
 """Equilibrium and moments (Maxwellian and dimensionless variables; Formula (1);
 polynomial equilibria f_i^eq = w_i P^(N)(v_i) with the m-th order Hermite
-expansion, N = m = 4).
+expansion, N = m: 4 for the models of Tables 2 and 3, 2 for the lower-order
+3D 19- and 15-velocity sets).
 
 Test infrastructure: see the package docstring.
 
@@ -81,11 +82,18 @@ def maxwell_hermite_coefficients(rho: torch.Tensor, u_hat: torch.Tensor, dth: to
     return a0, a1, a2, a3, a4
 
 
-def feq(vs: VelocitySet, rho: torch.Tensor, U: torch.Tensor, T: torch.Tensor) -> torch.Tensor:
-    """Discrete equilibrium f_i^eq = w_i sum_{n<=4} (1/n!) a^(n) : H^(n)(xi_i).
+def feq(vs: VelocitySet, rho: torch.Tensor, U: torch.Tensor, T: torch.Tensor,
+        order: int = None) -> torch.Tensor:
+    """Discrete equilibrium f_i^eq = w_i sum_{n<=N} (1/n!) a^(n) : H^(n)(xi_i).
 
-    rho, T have the grid shape; U has shape (D, *grid).  Returns (Q, *grid).
+    N = `order`, by default the model's order of accuracy m (N = m, as the
+    paragraph after Formula (5) asks for N >= m): the Hermite sum is simply
+    truncated after order N.  rho, T have the grid shape; U has shape
+    (D, *grid).  Returns (Q, *grid).
     """
+    N = vs.m if order is None else order
+    if not 0 <= N <= 4:
+        raise ValueError("equilibrium order must be 0..4")
     rho = torch.as_tensor(rho, dtype=torch.float64)
     U = torch.as_tensor(U, dtype=torch.float64)
     T = torch.as_tensor(T, dtype=torch.float64)
@@ -101,7 +109,7 @@ def feq(vs: VelocitySet, rho: torch.Tensor, U: torch.Tensor, T: torch.Tensor) ->
     fact = (1.0, 1.0, 2.0, 6.0, 24.0)
     Q = xi.shape[0]
     acc = None
-    for n in range(5):
+    for n in range(N + 1):
         Hn = H[n].reshape(Q, -1)           # (Q, D^n)
         An = A[n].reshape(r.shape[0], -1)  # (M, D^n)
         term = (Hn @ An.T) / fact[n]        # (Q, M)

@@ -58,6 +58,30 @@ TABLES = {"D2Q33": (TABLE2, TABLE2_C), "D3Q95": (TABLE3, TABLE3_C)}
 # n_max = 2m = 8 (the statement after Formula (8)).
 ORDER_M = 4
 
+# Lower-order 3D sets that the paper says the same construction gives (the
+# paragraph after Formula (10)): order m = 2, so Formula (5) up to n_max = 4,
+# Omega(2, 3) = 4 equations for three group weights and c (Formula (10)).
+# The paper prints no weights for them; the solve starts from least squares
+# at c = 1.  (group order, representative)
+LOWER_ORDER = {
+    "D3Q19": [(1, (0, 0, 0)), (6, (1, 0, 0)), (12, (1, 1, 0))],
+    "D3Q15": [(1, (0, 0, 0)), (6, (1, 0, 0)), (8, (1, 1, 1))],
+}
+LOWER_ORDER_M = 2
+
+
+def model_order(name: str) -> int:
+    """Order of accuracy m of a model; its equilibrium has order N = m (the
+    paragraph after Formula (5) requires N >= m)."""
+    return LOWER_ORDER_M if name in LOWER_ORDER else ORDER_M
+
+
+def group_table(name: str):
+    """[(group order, representative)] of a model, in table order."""
+    if name in LOWER_ORDER:
+        return list(LOWER_ORDER[name])
+    return [(o, r) for (o, r, _w) in TABLES[name][0]]
+
 
 def orbit(rep: Tuple[int, ...]) -> List[Tuple[int, ...]]:
     """All images of ``rep`` under coordinate permutations and sign flips,
@@ -114,6 +138,7 @@ class VelocitySet:
     group_sizes: List[int]
     W: np.ndarray            # (G,) group weights
     c: float
+    m: int = ORDER_M         # order of accuracy; the equilibrium has order N = m
 
     @property
     def Q(self) -> int:
@@ -135,10 +160,10 @@ class VelocitySet:
 
 
 def build_orbits(name: str):
-    table, _ = TABLES[name]
+    table = group_table(name)
     D = len(table[0][1])
     e_list, g_list = [], []
-    for g, (order, rep, _w) in enumerate(table):
+    for g, (order, rep) in enumerate(table):
         orb = orbit(rep)
         if len(orb) != order:
             raise AssertionError(f"{name} group {g}: orbit of {rep} has {len(orb)} points, table says {order}")
@@ -147,9 +172,12 @@ def build_orbits(name: str):
     return D, np.array(e_list, dtype=np.int64), np.array(g_list, dtype=np.int64)
 
 
-def orbit_moment_matrix(name: str, m: int = ORDER_M):
+def orbit_moment_matrix(name: str, m: int = None):
     """B[k, g] = sum over the orbit of group g of prod_alpha e_alpha^(a_k alpha),
-    and the order |a_k| of each equation."""
+    and the order |a_k| of each equation (Formula (5) up to n_max = 2m, by
+    default with the model's own m)."""
+    if m is None:
+        m = model_order(name)
     D, e, grp = build_orbits(name)
     idx = equation_indices(D, m)
     G = int(grp.max()) + 1
@@ -182,12 +210,18 @@ def solve_weights(name: str, tol: float = 1e-15, maxit: int = 60):
     """
     import mpmath
 
-    table, c0 = TABLES[name]
     _, B, order, rhs = orbit_moment_matrix(name)
-    G = len(table)
+    G = B.shape[1]
     if B.shape[0] != G + 1:
         raise AssertionError("system is not square")
-    x = np.array([w for (_o, _r, w) in table] + [c0], dtype=np.float64)
+    if name in TABLES:
+        table, c0 = TABLES[name]
+        x = np.array([w for (_o, _r, w) in table] + [c0], dtype=np.float64)
+    else:
+        # no printed values: least-squares weights at c = 1
+        c0 = 1.0
+        W0, *_ = np.linalg.lstsq(B * (c0 ** order)[:, None], rhs, rcond=None)
+        x = np.concatenate([W0, [c0]])
     for _ in range(maxit):
         W, c = x[:G], x[G]
         cp = c ** order
@@ -229,6 +263,6 @@ def velocity_set(name: str) -> VelocitySet:
     if name not in _CACHE:
         D, e, grp = build_orbits(name)
         W, c = solve_weights(name)
-        table, _ = TABLES[name]
-        _CACHE[name] = VelocitySet(name, D, e, grp, [t[0] for t in table], W, c)
+        _CACHE[name] = VelocitySet(name, D, e, grp, [t[0] for t in group_table(name)], W, c,
+                                   model_order(name))
     return _CACHE[name]

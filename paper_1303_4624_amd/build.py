@@ -18,13 +18,20 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(HERE, "liblbm.so")
-SOURCES = ["lbm_kernels.hip", "lbm_api.cpp", "lbm_model_host.cpp"]
+# One translation unit per model (and per precision for D3Q95), so that the
+# heavy kernel instantiations compile in parallel.
+SOURCES = ["lbm_kernels_d3q95_f32s.hip", "lbm_kernels_d3q95_f64.hip", "lbm_kernels_d2q33.hip",
+           "lbm_kernels_lower.hip", "lbm_kernels_common.hip", "lbm_api.cpp",
+           "lbm_model_host.cpp"]
 # Host-only sources compiled by the host C++ compiler (binary128 arithmetic).
 HOST_SOURCES = {"lbm_model_host.cpp"}
 ARCH = "gfx950"
 
+# -ffp-contract=off: no multiply-add is fused unless the source says fma(),
+# so every kernel that computes a quantity rounds it the same way (the
+# two-buffer and in-place updates agree bit for bit by construction).
 COMMON = [
-    "-O3", "-std=c++20", "-fPIC", "-fvisibility=hidden",
+    "-O3", "-std=c++20", "-fPIC", "-fvisibility=hidden", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", INCLUDE, "-I", CSRC,
 ]

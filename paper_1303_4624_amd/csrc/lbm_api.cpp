@@ -183,16 +183,10 @@ void fill_kparams(lbm_ctx* ctx) {
     k.T0 = ctx->T0;
     k.invT0 = 1.0 / ctx->T0;
     k.rho0 = ctx->prec == Prec::F32S ? ctx->rho0 : 0.0;
-    const double D = ctx->D;
     for (int g = 0; g < lbm::kMaxG; ++g) {
         const bool on = g < ctx->G;
-        const double X = on ? lbm::model_e2(ctx->model, g) / ctx->T0 : 0.0;
         k.W[g] = on ? ctx->W[g] : 0.0;
-        k.K1[g] = 0.5 * (X - D);
-        k.K2[g] = 0.25 * (D + 2.0 - X);
-        k.K3[g] = 0.125 * (X * X - 2.0 * (D + 2.0) * X + D * (D + 2.0));
-        k.K4[g] = 0.5 * (X - D - 2.0);
-        k.K5[g] = 0.25 * (X - D - 4.0);
+        k.X[g] = on ? lbm::model_e2(ctx->model, g) / ctx->T0 : 0.0;
     }
 }
 
@@ -233,7 +227,7 @@ LBM_API const char* lbm_last_error(const lbm_ctx* ctx) {
 LBM_API int lbm_velocity_set(int D, int Q, int32_t* e, double* w, double* c) {
     ModelId m;
     if (!lbm::model_from_shape(D, Q, m))
-        return fail(nullptr, LBM_E_UNSUPPORTED, "only D=2,Q=33 and D=3,Q=95 are supported");
+        return fail(nullptr, LBM_E_UNSUPPORTED, "supported models: D=2,Q=33; D=3,Q=95; D=3,Q=19; D=3,Q=15");
     double W[lbm::kMaxG], cc;
     std::string err;
     if (!lbm::model_solve(m, W, &cc, err)) return fail(nullptr, LBM_E_INVALID, err);
@@ -299,7 +293,7 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
     if (!e || !w || !extent) return fail(nullptr, LBM_E_INVALID, "e, w and extent must be given");
     ModelId m;
     if (!lbm::model_from_shape(D, Q, m))
-        return fail(nullptr, LBM_E_UNSUPPORTED, "only D=2,Q=33 and D=3,Q=95 are supported");
+        return fail(nullptr, LBM_E_UNSUPPORTED, "supported models: D=2,Q=33; D=3,Q=95; D=3,Q=19; D=3,Q=15");
     if (!lbm::model_matches(m, e))
         return fail(nullptr, LBM_E_UNSUPPORTED,
                     "velocity list is not the canonical order of the model");
@@ -916,12 +910,14 @@ LBM_API int lbm_adjoint(lbm_ctx* ctx, int n, int k, int keep, const void* ckpt,
             segmom = ck + C.off_tail + static_cast<size_t>(t0 - C.t_keep) * C.mom_step;
         } else {
             // recompute the segment from its checkpoint (read in place),
-            // storing the moments of every step
+            // storing the moments of every step; the last step stores its
+            // moments only (its state is snapshot s + 1, which nothing here
+            // reads again)
             const void* src = ck + s * ck_stride;
             int dst = fr[0];
             for (int j = 0; j < len; ++j) {
-                e = lbm::launch_step(ctx->model, ctx->prec, kab, src, B[dst],
-                                     mom + j * L.mom_step, st);
+                e = lbm::launch_step(ctx->model, ctx->prec, kab, src,
+                                     j + 1 < len ? B[dst] : nullptr, mom + j * L.mom_step, st);
                 if (e != hipSuccess) return fail_hip(ctx, e, "recompute step kernel");
                 src = B[dst];
                 dst = (dst == fr[0]) ? fr[1] : fr[0];

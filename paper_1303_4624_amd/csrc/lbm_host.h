@@ -17,6 +17,8 @@ int model_groups(ModelId m);
 int model_group_of(ModelId m, int i);
 int model_e(ModelId m, int i, int k);
 int model_e2(ModelId m, int g);
+// Order of accuracy m of a compiled model (its equilibrium has order N = m).
+int model_order(ModelId m);
 // True if e (int32[Q][D]) is the canonical velocity list of the model.
 bool model_matches(ModelId m, const int32_t* e);
 // Largest absolute residual of Formula (5) at group weights W and speed c.

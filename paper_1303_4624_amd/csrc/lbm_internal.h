@@ -20,12 +20,6 @@
 
 namespace lbm {
 
-// Per-context constants, passed to every kernel by value.
-//
-// The equilibrium is evaluated per symmetry group g with X_g = |e_g|^2 / T0;
-// the X-only parts of its coefficients are precomputed here:
-//   K1 = (X - D)/2, K2 = (D + 2 - X)/4, K3 = (X^2 - 2(D + 2)X + D(D + 2))/8,
-//   K4 = (X - D - 2)/2, K5 = (X - D - 4)/4.
 // Elements added to every population run of a row (run stride = nx + pad).
 #ifndef LBM_RUN_PAD
 #define LBM_RUN_PAD 0
@@ -83,6 +77,10 @@ constexpr int kFormAB = 0;        // two buffers: run i of cell c
 constexpr int kFormSwapped = 1;   // in place, after an even number of steps: run opp(i) of c
 constexpr int kFormPushed = 2;    // in place, after an odd number of steps: run i of c + e_i
 
+// Per-context constants, passed to every kernel by value.  Per group only
+// the weight W_g and X_g = |e_g|^2 / T0 are arguments (argument values live
+// in scalar registers; the kernels form every other coefficient of the
+// equilibrium per cell as a polynomial in X).
 struct KParams {
     int nx, ny, nz;           // nz = 1 in 2D
     int form;                 // storage form of the state the kernel reads or writes
@@ -100,7 +98,7 @@ struct KParams {
     double invT0;             // 1 / T0
     double rho0;              // shift reference (FP32-shifted storage)
     double W[kMaxG];          // group weights
-    double K1[kMaxG], K2[kMaxG], K3[kMaxG], K4[kMaxG], K5[kMaxG];
+    double X[kMaxG];          // |e_g|^2 / T0 per group
     int hold_lo, hold_hi;     // planes of the slowest axis held at f^eq(hold[0] / hold[1])
     FixedState hold[2];
 };
@@ -128,11 +126,16 @@ hipError_t launch_set_pop(ModelId m, Prec p, const KParams& kp, const double* fi
                           hipStream_t s);
 hipError_t launch_get_pop(ModelId m, Prec p, const KParams& kp, const void* f, double* fout,
                           hipStream_t s);
+// One update step from src into dst.  mom_out != nullptr: also store the
+// step's D+2 moments (recomputation for the adjoint).  dst == nullptr (with
+// mom_out): gather and store the moments only, no populations (the last
+// recomputed step of a segment, whose state the next checkpoint holds).
 hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, void* dst,
                        void* mom_out, hipStream_t s);
 // In-place step (AA pattern): push = true reads the swapped form and writes
 // the pushed form, push = false the reverse.  mom_out != nullptr: also store
-// the step's D+2 moments (as launch_step does; fixed planes are then ignored).
+// the step's D+2 moments (as launch_step does; held planes store the moments
+// of their held state).
 hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool push,
                           void* mom_out, hipStream_t s);
 // Copy of the state f, stored in form kp.form, into the two-buffer form.
@@ -162,5 +165,33 @@ hipError_t launch_sum_partials(const double* part, long long n, int stride, int 
 
 // Sizes used by the API layer for its buffers.
 long long step_blocks(ModelId m, Prec p, const KParams& kp);
+
+// The launchers of one model and precision (defined with the kernels in
+// lbm_kernels.h, instantiated once per model and precision in its own
+// translation unit; the launch_* functions above dispatch to them).
+template <class M, Prec P>
+struct ModelKernels {
+    static hipError_t init(const KParams& kp, const double* rho, const double* U, const double* T,
+                           void* f, hipStream_t s);
+    static hipError_t set_pop(const KParams& kp, const double* fin, void* f, hipStream_t s);
+    static hipError_t get_pop(const KParams& kp, const void* f, double* fout, hipStream_t s);
+    static hipError_t step(const KParams& kp, const void* src, void* dst, void* mom_out,
+                           hipStream_t s);
+    static hipError_t step_aa(const KParams& kp, void* f, bool push, void* mom_out,
+                              hipStream_t s);
+    static hipError_t to_ab(const KParams& kp, const void* f, void* out, hipStream_t s);
+    static hipError_t from_ab(const KParams& kp, const void* f, void* out, hipStream_t s);
+    static hipError_t moments(const KParams& kp, const void* f, double* rho, double* U,
+                              double* T, hipStream_t s);
+    static hipError_t conservation(const KParams& kp, const void* f, double* partials,
+                                   hipStream_t s);
+    static hipError_t lambda_init(const KParams& kp, const void* fn, const double* dLdrho,
+                                  void* lam, double* partK, hipStream_t s);
+    static hipError_t adjoint_step(const KParams& kp, const void* lam_src, void* lam_dst,
+                                   const void* mom, double* partA, const void* mark_state,
+                                   double* partM, hipStream_t s);
+    static hipError_t dT_init(const KParams& kp, const void* lam0, const double* rho,
+                              const double* U, const double* T, double* dT, hipStream_t s);
+};
 
 }  // namespace lbm

@@ -1,5 +1,9 @@
-// lbm_kernels.hip - HIP kernels for CDNA4 (gfx950) of the thermal lattice
-// Boltzmann update with the D2Q33 / D3Q95 on-lattice models.
+// lbm_kernels.h - HIP kernels for CDNA4 (gfx950) of the thermal lattice
+// Boltzmann update with the on-lattice models (D2Q33, D3Q95 of 4th order;
+// the lower-order D3Q19, D3Q15), and the launchers of one model and
+// precision (ModelKernels<M, P>).  Included only by the lbm_kernels_*.hip
+// translation units, each of which instantiates the launchers of one model
+// (and precision), so that the models compile in parallel.
 //
 // Data layout: row-blocked.  The Q populations of a group of consecutive
 // grid rows are contiguous, population-major (see PopAt / row_base), cells
@@ -23,17 +27,20 @@
 // Streaming: two buffers (k_step: pull from one, store to the other) or one
 // buffer updated in place (k_step_aa, the AA pattern).
 //
-// Equilibrium: the 4th-order Hermite expansion of the Maxwellian, written as
-// a polynomial in s = xi_i . u_hat for each symmetry group (|e_i|^2 is
+// Equilibrium: the Hermite expansion of the Maxwellian of order N (N = 4 for
+// the 4th-order models, N = 2 for the 2nd-order ones), written as a
+// polynomial in s = xi_i . u_hat for each symmetry group (|e_i|^2 is
 // constant on a group, so every coefficient except s is per group):
-//   P_i = 1 + h_i,  h_i = a0 + s (a1 + s (a2 + s (1/6 + s/24)))
+//   N = 4:  P_i = 1 + h_i,  h_i = a0 + s (a1 + s (a2 + s (1/6 + s/24)))
 //   a0 = (-u2 + d (X - D)) / 2
 //        + (3 u2^2 + 6 d (D + 2 - X) u2 + 3 d^2 (X^2 - 2 (D + 2) X + D (D + 2))) / 24
 //   a1 = 1 - u2/2 + d (X - D - 2)/2,   a2 = 1/2 - u2/4 + d (X - D - 4)/4
+//   N = 2:  h_i = (-u2 + d (X - D)) / 2 + s (1 + s/2)
 // with xi_i = e_i / c_s, c_s^2 = T0, u_hat = U / c_s, u2 = |u_hat|^2,
 // X = |xi_i|^2 and d = T/T0 - 1, so s = e_i . U / T0.  This is the
-// contraction of sum_{n<=4} a^(n):H^(n)(xi)/n! with the Hermite coefficients
-// of the Maxwellian, collected in powers of s.
+// contraction of sum_{n<=N} a^(n):H^(n)(xi)/n! with the Hermite coefficients
+// of the Maxwellian, collected in powers of s.  Per cell the coefficients
+// are formed once as polynomials in X (XPoly); per group only X_g enters.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -56,10 +63,12 @@ namespace {
 #ifndef LBM_ADJ_SCHED_BARRIER
 #define LBM_ADJ_SCHED_BARRIER 0
 #endif
-// Occupancy target of the adjoint kernel: 3 waves per SIMD keeps it at
-// <= 168 VGPRs without spills (4 % faster than letting it grow to 256).
+// Occupancy target of the FP32-shifted adjoint kernel (waves per SIMD).  It
+// needs about 190 VGPRs (the 95 gathered adjoint values, float64 group sums,
+// the per-cell equilibrium polynomials); a target of 3 waves (168 VGPRs)
+// makes it spill to scratch memory.
 #ifndef LBM_ADJ_WAVES
-#define LBM_ADJ_WAVES 3
+#define LBM_ADJ_WAVES 2
 #endif
 #ifndef LBM_F32_WAVES
 #define LBM_F32_WAVES 1
@@ -77,6 +86,7 @@ namespace {
 #ifndef LBM_AA_NT_LOCAL
 #define LBM_AA_NT_LOCAL 1
 #endif
+
 #ifndef LBM_F32S_SUM64
 #define LBM_F32S_SUM64 1
 #endif
@@ -116,6 +126,15 @@ struct F32ST {
     static constexpr bool shifted = true;
     static constexpr int waves = LBM_F32_WAVES;
     static constexpr int adj_waves = LBM_ADJ_WAVES;
+};
+
+template <Prec P>
+struct PrecOf {
+    using type = F64T;
+};
+template <>
+struct PrecOf<Prec::F32S> {
+    using type = F32ST;
 };
 
 // (v mod n) for v in [-kMaxDisp, n - 1 + kMaxDisp]; n is wave-uniform.
@@ -408,21 +427,68 @@ __device__ __forceinline__ Macro macro_from_sums(const KParams& k, double m0, do
     return m;
 }
 
-// Coefficients of h in powers of s for group g (float64).
+// Coefficients of h in powers of s for one group (float64), from the
+// per-cell polynomials in X = |xi|^2 of the Hermite expansion of order N:
+//   N = 4: a0 = a00 + X (a01 + X a02), a1 = a10 + a11 X, a2 = a20 + a21 X
+//          (the a0, a1, a2 of the file header expanded in X);
+//   N = 2: a0 = a00 + X a01, a1 = 1, a2 = 1/2.
 struct GCoef {
     double a0, a1, a2;
 };
-__device__ __forceinline__ GCoef group_coef(const KParams& k, int g, double u2, double d) {
-    GCoef c;
-    c.a0 = -0.5 * u2 + 0.125 * u2 * u2 + d * (k.K1[g] + u2 * k.K2[g] + d * k.K3[g]);
-    c.a1 = 1.0 - 0.5 * u2 + d * k.K4[g];
-    c.a2 = 0.5 - 0.25 * u2 + d * k.K5[g];
-    return c;
+template <int D, int N>
+struct XPoly {
+    double a00, a01, a02, a10, a11, a20, a21;
+    __device__ __forceinline__ XPoly(double u2, double d) {
+        constexpr double Dd = D;
+        if constexpr (N == 4) {
+            a00 = -0.5 * u2 + 0.125 * u2 * u2 +
+                  d * (-0.5 * Dd + u2 * (0.25 * (Dd + 2.0)) + d * (0.125 * Dd * (Dd + 2.0)));
+            a01 = d * (0.5 - 0.25 * u2 - d * (0.25 * (Dd + 2.0)));
+            a02 = 0.125 * d * d;
+            a10 = 1.0 - 0.5 * u2 - d * (0.5 * (Dd + 2.0));
+            a11 = 0.5 * d;
+            a20 = 0.5 - 0.25 * u2 - d * (0.25 * (Dd + 4.0));
+            a21 = 0.25 * d;
+        } else {
+            static_assert(N == 2, "equilibrium order 2 or 4");
+            a00 = -0.5 * u2 - d * (0.5 * Dd);
+            a01 = 0.5 * d;
+            a02 = 0.0;
+            a10 = 1.0;
+            a11 = 0.0;
+            a20 = 0.5;
+            a21 = 0.0;
+        }
+    }
+    __device__ __forceinline__ GCoef at(double X) const {
+        GCoef c;
+        if constexpr (N == 4) {
+            c.a0 = a00 + X * (a01 + X * a02);
+            c.a1 = a10 + a11 * X;
+            c.a2 = a20 + a21 * X;
+        } else {
+            c.a0 = a00 + X * a01;
+            c.a1 = 1.0;
+            c.a2 = 0.5;
+        }
+        return c;
+    }
+};
+
+// X_g = |e_g|^2 / T0 of group g.
+template <class M, int g>
+__device__ __forceinline__ double group_x(const KParams& k) {
+    return k.X[g];
 }
 
-template <class R>
+// h(s) of order N with the group's coefficients (a1, a2 unused for N = 2,
+// where they are the constants 1 and 1/2).
+template <int N, class R>
 __device__ __forceinline__ R horner_h(R a0, R a1, R a2, R s) {
-    return a0 + s * (a1 + s * (a2 + s * (R(1.0 / 6.0) + s * R(1.0 / 24.0))));
+    if constexpr (N == 4)
+        return fma(s, fma(s, fma(s, fma(s, R(1.0 / 24.0), R(1.0 / 6.0)), a2), a1), a0);
+    else
+        return fma(s, fma(s, R(0.5), R(1)), a0);
 }
 
 // s_i = e_i . ut with compile-time integer components.
@@ -430,8 +496,8 @@ template <int ex, int ey, int ez, class R>
 __device__ __forceinline__ R edot(R ux, R uy, R uz) {
     R s = R(0);
     if constexpr (ex != 0) s = R(ex) * ux;
-    if constexpr (ey != 0) s = (ex != 0) ? s + R(ey) * uy : R(ey) * uy;
-    if constexpr (ez != 0) s = (ex != 0 || ey != 0) ? s + R(ez) * uz : R(ez) * uz;
+    if constexpr (ey != 0) s = (ex != 0) ? fma(R(ey), uy, s) : R(ey) * uy;
+    if constexpr (ez != 0) s = (ex != 0 || ey != 0) ? fma(R(ez), uz, s) : R(ez) * uz;
     return s;
 }
 
@@ -481,14 +547,16 @@ __device__ __forceinline__ void feq_cell(const KParams& k, double r, double ux, 
     const double d = T * k.invT0 - 1.0;
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
+    const XPoly<M::D, M::N> xp(u2, d);
     static_for<M::G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        const GCoef gc = group_coef(k, g, u2, d);
+        const GCoef gc = xp.at(group_x<M, g>(k));
         const double w = k.W[g];
         static_for<M::table.gsize[g]>([&](auto JI) {
             constexpr int i = M::table.gstart[g] + decltype(JI)::value;
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
-            const double h = horner_h(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
+            const double h =
+                horner_h<M::N>(gc.a0, gc.a1, gc.a2, edot<ex, ey, ez>(utx, uty, utz));
             if constexpr (P::shifted)
                 emit(std::integral_constant<int, i>{}, S(w * (r - k.rho0) + w * r * h));
             else
@@ -512,36 +580,71 @@ __device__ __forceinline__ void store_feq(typename P::S* __restrict__ f, const K
 // Moments, equilibrium and BGK relaxation of one cell's incoming values v;
 // emit(I, value) receives post-collision population I::value, in increasing
 // order.  Returns the cell's macroscopic values.
-template <class M, class P, class Emit>
-__device__ __forceinline__ Macro relax_cell(const KParams& k, const typename P::S (&v)[M::Q],
-                                            Emit&& emit) {
-    using R = typename P::S;
-    constexpr int Q = M::Q;
-    constexpr int G = M::G;
-    constexpr int D = M::D;
+// Macroscopic values of one cell's incoming values v (the sums in velocity
+// order, in P::Acc).
+template <class M, class P>
+__device__ __forceinline__ Macro cell_macro(const KParams& k, const typename P::S (&v)[M::Q]) {
     using A = typename P::Acc;
     A m0 = A(0), jx = A(0), jy = A(0), jz = A(0), en = A(0);
-    static_for<Q>([&](auto I) {
+    static_for<M::Q>([&](auto I) {
         constexpr int i = decltype(I)::value;
         constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
         constexpr int ee = M::table.e2[M::table.group[i]];
         const A vi = A(v[i]);
         m0 += vi;
-        if constexpr (ex != 0) jx += A(ex) * vi;
-        if constexpr (ey != 0) jy += A(ey) * vi;
-        if constexpr (ez != 0) jz += A(ez) * vi;
-        if constexpr (ee != 0) en += A(ee) * vi;
+        if constexpr (ex != 0) jx = fma(A(ex), vi, jx);
+        if constexpr (ey != 0) jy = fma(A(ey), vi, jy);
+        if constexpr (ez != 0) jz = fma(A(ez), vi, jz);
+        if constexpr (ee != 0) en = fma(A(ee), vi, en);
     });
+    return macro_from_sums<M::D, P::shifted>(k, m0, jx, jy, jz, en);
+}
 
-    const Macro mc = macro_from_sums<D, P::shifted>(k, m0, jx, jy, jz, en);
+// cell_macro with its results pinned in registers: an empty asm statement
+// that "modifies" them ends the compiler's view of how they were computed.
+// Every update kernel takes its macroscopic values through this, so that the
+// arithmetic after it (and the contraction of its multiply-adds into fused
+// ones) is the same in the two-buffer and the in-place kernels and their
+// results agree bit for bit.  It also keeps the in-place kernels, whose
+// stores are predicated on active lanes, from moving the moment sums under
+// that branch, where they were computed one sum after another with every
+// converted value held live (register spills).
+template <class M, class P>
+__device__ __forceinline__ Macro cell_macro_pinned(const KParams& k,
+                                                   const typename P::S (&v)[M::Q]) {
+    Macro mc = cell_macro<M, P>(k, v);
+    asm volatile("" : "+v"(mc.rho), "+v"(mc.dr), "+v"(mc.ux), "+v"(mc.uy), "+v"(mc.uz),
+                 "+v"(mc.d), "+v"(mc.u2));
+    return mc;
+}
+
+template <class M, class P, class Emit>
+__device__ __forceinline__ void relax_with(const KParams& k, const typename P::S (&v)[M::Q],
+                                           const Macro& mc, Emit&& emit);
+
+template <class M, class P, class Emit>
+__device__ __forceinline__ Macro relax_cell(const KParams& k, const typename P::S (&v)[M::Q],
+                                            Emit&& emit) {
+    const Macro mc = cell_macro_pinned<M, P>(k, v);
+    relax_with<M, P>(k, v, mc, emit);
+    return mc;
+}
+
+template <class M, class P, class Emit>
+__device__ __forceinline__ void relax_with(const KParams& k, const typename P::S (&v)[M::Q],
+                                           const Macro& mc, Emit&& emit) {
+    using R = typename P::S;
+    constexpr int G = M::G;
+    constexpr int D = M::D;
     const R utx = R(mc.ux * k.invT0), uty = R(mc.uy * k.invT0), utz = R(mc.uz * k.invT0);
     const double wr = k.omega_eff * mc.rho;
     const double wd = k.omega_eff * mc.dr;
     const R omc = R(k.omc);
+    const XPoly<D, M::N> xp(mc.u2, mc.d);
 
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        const GCoef gc = group_coef(k, g, mc.u2, mc.d);
+        const GCoef gc = xp.at(group_x<M, g>(k));
         const R a0 = R(gc.a0), a1 = R(gc.a1), a2 = R(gc.a2);
         const R ca = R(wr * k.W[g]);
         const R cb = R(wd * k.W[g]);
@@ -549,7 +652,7 @@ __device__ __forceinline__ Macro relax_cell(const KParams& k, const typename P::
             constexpr int i = M::table.gstart[g] + decltype(JI)::value;
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const R s = edot<ex, ey, ez>(utx, uty, utz);
-            const R h = horner_h(a0, a1, a2, s);
+            const R h = horner_h<M::N>(a0, a1, a2, s);
             R out;
             if constexpr (P::shifted) {
                 out = fma(omc, v[i], fma(ca, h, cb));
@@ -559,7 +662,6 @@ __device__ __forceinline__ Macro relax_cell(const KParams& k, const typename P::
             emit(std::integral_constant<int, i>{}, out);
         });
     });
-    return mc;
 }
 
 // Forward update, two buffers: pull gather from src, relax, store to dst.
@@ -588,12 +690,16 @@ __device__ __forceinline__ void store_held_moments(const KParams& k, const Cell&
     mom[(M::D + 1) * k.N + cl.c] = S(st.T * k.invT0 - 1.0);
 }
 
-template <class M, class P, bool STORE_MOM, bool HOLD>
+// POP = false (with STORE_MOM): the step's moments only, no populations are
+// relaxed or stored (the last recomputed step of a checkpoint segment,
+// whose post-collision state the next snapshot already holds).
+template <class M, class P, bool STORE_MOM, bool HOLD, bool POP = true>
 __global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
 void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst, KParams k,
             typename P::S* __restrict__ mom) {
     using S = typename P::S;
     constexpr int D = M::D;
+    static_assert(POP || STORE_MOM, "a step stores populations, moments or both");
     const Cell cl = row_cell(k);
 
     if constexpr (HOLD) {
@@ -601,9 +707,11 @@ void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ d
         const int L = (D == 3) ? k.nz : k.ny;
         if (sl < k.hold_lo || sl >= L - k.hold_hi) {
             const FixedState& st = (sl < k.hold_lo) ? k.hold[0] : k.hold[1];
-            PlaneWriter<S> out_w(dst, k, cl, M::Q);
-            feq_cell<M, P>(k, st.rho, st.U[0], st.U[1], st.U[2], st.T,
-                           [&](auto, S val) { out_w.put(val); });
+            if constexpr (POP) {
+                PlaneWriter<S> out_w(dst, k, cl, M::Q);
+                feq_cell<M, P>(k, st.rho, st.U[0], st.U[1], st.U[2], st.T,
+                               [&](auto, S val) { out_w.put(val); });
+            }
             if constexpr (STORE_MOM) store_held_moments<M, P>(k, cl, st, mom);
             return;
         }
@@ -611,8 +719,13 @@ void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ d
 
     S v[M::Q];
     gather<M, +1>(src, k, cl, v);
-    PlaneWriter<S> out_w(dst, k, cl, M::Q);
-    const Macro mc = relax_cell<M, P>(k, v, [&](auto, S val) { out_w.put(val); });
+    Macro mc;
+    if constexpr (POP) {
+        PlaneWriter<S> out_w(dst, k, cl, M::Q);
+        mc = relax_cell<M, P>(k, v, [&](auto, S val) { out_w.put(val); });
+    } else {
+        mc = cell_macro_pinned<M, P>(k, v);
+    }
 
     if constexpr (STORE_MOM) {
         if (cl.active) {
@@ -678,7 +791,8 @@ void k_step_aa(typename P::S* f, KParams k, typename P::S* __restrict__ mom) {
         else
             v[i] = load_pop<S>(ad.template at<i, 0, 0, 0>());
     });
-    const Macro mc = relax_cell<M, P>(k, v, put);
+    const Macro mc = cell_macro_pinned<M, P>(k, v);
+    relax_with<M, P>(k, v, mc, put);
     if constexpr (STORE_MOM) {
         if (cl.active) {
             mom[cl.c] = S(P::shifted ? mc.dr : mc.rho);
@@ -833,30 +947,6 @@ __global__ __launch_bounds__(kBlock) void k_conservation(const typename P::S* __
     block_sum<D + 2>(acc, partials + static_cast<long long>(blockIdx.x) * (D + 2), false);
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill_zero(double* p, long long n) {
-    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0.0;
-}
-
-// out[q] = sum_j part[j*stride + q] for q < count, one block, fixed order.
-__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ part,
-                                                         long long n, int stride, int count,
-                                                         double* __restrict__ out) {
-    __shared__ double sh[kBlock];
-    for (int q = 0; q < count; ++q) {
-        double s = 0.0;
-        for (long long j = threadIdx.x; j < n; j += blockDim.x) s += part[j * stride + q];
-        sh[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-            if (static_cast<int>(threadIdx.x) < w) sh[threadIdx.x] += sh[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[q] = sh[0];
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------------------
 // Adjoint.
 //
@@ -889,22 +979,69 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     block_sum<1>(acc, partK + blockIdx.x, false);
 }
 
-// Derivative coefficients of P = 1 + h with respect to s, u2 and d, per group:
-//   P_s  = a1 + s (2 a2 + s (1/2 + s/6))
-//   P_u2 = b0 + s (-1/2 - s/4),          b0 = -1/2 + u2/4 + d (D + 2 - X)/4
-//   P_d  = c0 + s (c1 + s c2),            c0 = (X - D)/2 + (D + 2 - X) u2/4
-//                                              + d (X^2 - 2 (D + 2) X + D (D + 2))/4
-//                                         c1 = (X - D - 2)/2, c2 = (X - D - 4)/4
+// Derivative coefficients of P = 1 + h with respect to s, u2 and d, per group.
+//   N = 4: P_s  = a1 + s (2 a2 + s (1/2 + s/6))
+//          P_u2 = b0 + s (-1/2 - s/4),     b0 = -1/2 + u2/4 + d (D + 2 - X)/4
+//          P_d  = c0 + s (c1 + s c2),       c0 = (X - D)/2 + (D + 2 - X) u2/4
+//                                                + d (X^2 - 2 (D + 2) X + D (D + 2))/4
+//                                           c1 = (X - D - 2)/2, c2 = (X - D - 4)/4
+//   N = 2: P_s = 1 + s, P_u2 = -1/2, P_d = (X - D)/2.
+// Per cell they are polynomials in X (XDer), per group only X_g enters.
 struct GDer {
     double b0, c0, c1, c2;
 };
-__device__ __forceinline__ GDer group_der(const KParams& k, int g, double u2, double d) {
-    GDer c;
-    c.b0 = -0.5 + 0.25 * u2 + d * k.K2[g];
-    c.c0 = k.K1[g] + u2 * k.K2[g] + 2.0 * d * k.K3[g];
-    c.c1 = k.K4[g];
-    c.c2 = k.K5[g];
-    return c;
+template <int D, int N>
+struct XDer {
+    double b00, b01, c00, c01, c02;
+    __device__ __forceinline__ XDer(double u2, double d) {
+        constexpr double Dd = D;
+        if constexpr (N == 4) {
+            b00 = -0.5 + 0.25 * u2 + d * (0.25 * (Dd + 2.0));
+            b01 = -0.25 * d;
+            c00 = -0.5 * Dd + u2 * (0.25 * (Dd + 2.0)) + d * (0.25 * Dd * (Dd + 2.0));
+            c01 = 0.5 - 0.25 * u2 - d * (0.5 * (Dd + 2.0));
+            c02 = 0.25 * d;
+        } else {
+            static_assert(N == 2, "equilibrium order 2 or 4");
+            b00 = -0.5;
+            b01 = 0.0;
+            c00 = -0.5 * Dd;
+            c01 = 0.5;
+            c02 = 0.0;
+        }
+    }
+    __device__ __forceinline__ GDer at(double X) const {
+        GDer c;
+        if constexpr (N == 4) {
+            c.b0 = b00 + b01 * X;
+            c.c0 = c00 + X * (c01 + X * c02);
+            c.c1 = 0.5 * X - 0.5 * (D + 2.0);
+            c.c2 = 0.25 * X - 0.25 * (D + 4.0);
+        } else {
+            c.b0 = -0.5;
+            c.c0 = c00 + X * c01;
+            c.c1 = 0.0;
+            c.c2 = 0.0;
+        }
+        return c;
+    }
+};
+
+// P_s, P_u2, P_d of order N from the group's coefficients.
+template <int N, class R>
+__device__ __forceinline__ R eq_ps(R a1, R a2x2, R s) {
+    if constexpr (N == 4) return fma(s, fma(s, fma(s, R(1.0 / 6.0), R(0.5)), a2x2), a1);
+    else return R(1) + s;
+}
+template <int N, class R>
+__device__ __forceinline__ R eq_pu(R b0, R s) {
+    if constexpr (N == 4) return fma(s, fma(s, R(-0.25), R(-0.5)), b0);
+    else return R(-0.5);
+}
+template <int N, class R>
+__device__ __forceinline__ R eq_pd(R c0, R c1, R c2, R s) {
+    if constexpr (N == 4) return fma(s, fma(s, c2, c1), c0);
+    else return c0;
 }
 
 // One transposed step.  mu_i = lambda^{t+1}_i(x + e_i); the moments of f^t at x
@@ -984,10 +1121,13 @@ void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict
     // slightly different model than the forward step and bias the omega
     // gradient, which relies on <lambda^t, f*^t> staying constant.
     double s0 = 0.0, su2 = 0.0, sd = 0.0, ssx = 0.0, ssy = 0.0, ssz = 0.0;
+    const XPoly<D, M::N> xp(u2, d);
+    const XDer<D, M::N> xd(u2, d);
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        const GCoef gc = group_coef(k, g, u2, d);
-        const GDer gd = group_der(k, g, u2, d);
+        const double X = group_x<M, g>(k);
+        const GCoef gc = xp.at(X);
+        const GDer gd = xd.at(X);
         const R a0 = R(gc.a0), a1 = R(gc.a1), a2 = R(gc.a2), a2x2 = R(2.0 * gc.a2);
         const R b0 = R(gd.b0), c0 = R(gd.c0), c1 = R(gd.c1), c2 = R(gd.c2);
         // sum mu P = sum mu + sum mu h with P = 1 + h: the O(1) part is summed in
@@ -998,10 +1138,10 @@ void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict
             constexpr int i = M::table.gstart[g] + decltype(JI)::value;
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const R s = edot<ex, ey, ez>(utx, uty, utz);
-            const R h = a0 + s * (a1 + s * (a2 + s * (R(1.0 / 6.0) + s * R(1.0 / 24.0))));
-            const R ps = a1 + s * (a2x2 + s * (R(0.5) + s * R(1.0 / 6.0)));
-            const R pu = b0 + s * (R(-0.5) - s * R(0.25));
-            const R pd = c0 + s * (c1 + s * c2);
+            const R h = horner_h<M::N>(a0, a1, a2, s);
+            const R ps = eq_ps<M::N>(a1, a2x2, s);
+            const R pu = eq_pu<M::N>(b0, s);
+            const R pd = eq_pd<M::N>(c0, c1, c2, s);
             tm += static_cast<double>(mu[i]);
             if constexpr (MARK) tb = fma(mu[i], load_pop<S>(mark_at.template at<i, 0, 0, 0>()), tb);
             t0 = fma(mu[i], h, t0);
@@ -1100,16 +1240,17 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
     const PopAt<M, kFormAB> pa(k, c);
+    const XDer<D, M::N> xd(u2, d);
     double sd = 0.0;
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        const GDer gd = group_der(k, g, u2, d);
+        const GDer gd = xd.at(group_x<M, g>(k));
         double tg = 0.0;
         static_for<M::table.gsize[g]>([&](auto JI) {
             constexpr int i = M::table.gstart[g] + decltype(JI)::value;
             constexpr int ex = M::table.e[i][0], ey = M::table.e[i][1], ez = M::table.e[i][2];
             const double s = edot<ex, ey, ez>(utx, uty, utz);
-            const double pd = gd.c0 + s * (gd.c1 + s * gd.c2);
+            const double pd = eq_pd<M::N>(gd.c0, gd.c1, gd.c2, s);
             tg += static_cast<double>(lam[pa.template at<i>()]) * pd;
         });
         sd += k.W[g] * tg;
@@ -1117,21 +1258,9 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
     dT[c] = r * k.invT0 * sd;
 }
 
-template <class F>
-hipError_t with_types(ModelId m, Prec p, F&& f) {
-    if (m == ModelId::D2Q33) {
-        if (p == Prec::F64) return f(D2Q33{}, F64T{});
-        return f(D2Q33{}, F32ST{});
-    }
-    if (p == Prec::F64) return f(D3Q95{}, F64T{});
-    return f(D3Q95{}, F32ST{});
-}
-
 inline unsigned cell_blocks(long long N) {
     return static_cast<unsigned>((N + kBlock - 1) / kBlock);
 }
-
-}  // namespace
 
 static_assert(F64T::max_block == LBM_F64_MAXB && F32ST::max_block == LBM_STEP_MAXB,
               "step_max_threads (host) and the kernels' launch bounds must agree");
@@ -1152,224 +1281,184 @@ hipError_t with_initial_form(const KParams& kp, F&& f) {
     return f(std::integral_constant<int, kFormAB>{});
 }
 
-hipError_t launch_init(ModelId m, Prec p, const KParams& kp, const double* rho, const double* U,
-                       const double* T, void* f, hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        return with_initial_form(kp, [&](auto F) {
-            hipLaunchKernelGGL((k_init<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
-                               dim3(kBlock), 0, s, rho, U, T, static_cast<typename P::S*>(f), kp);
-            return hipGetLastError();
-        });
-    });
-}
+}  // namespace
 
-hipError_t launch_set_pop(ModelId m, Prec p, const KParams& kp, const double* fin, void* f,
-                          hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        return with_initial_form(kp, [&](auto F) {
-            hipLaunchKernelGGL((k_set_pop<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
-                               dim3(kBlock), 0, s, fin, static_cast<typename P::S*>(f), kp);
-            return hipGetLastError();
-        });
-    });
-}
-
-hipError_t launch_get_pop(ModelId m, Prec p, const KParams& kp, const void* f, double* fout,
-                          hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        return with_form(kp, [&](auto F) {
-            hipLaunchKernelGGL((k_get_pop<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
-                               dim3(kBlock), 0, s, static_cast<const typename P::S*>(f), fout, kp);
-            return hipGetLastError();
-        });
-    });
-}
-
-hipError_t launch_step(ModelId m, Prec p, const KParams& kp, const void* src, void* dst,
-                       void* mom_out, hipStream_t s) {
-    const long long blocks = step_blocks(m, p, kp);
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        using S = typename P::S;
-        const dim3 grid(static_cast<unsigned>(blocks));
-        if (mom_out && kp.hold_lo + kp.hold_hi > 0) {
-            hipLaunchKernelGGL((k_step<M, P, true, true>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
-                               static_cast<const S*>(src), static_cast<S*>(dst), kp,
-                               static_cast<S*>(mom_out));
-        } else if (mom_out) {
-            hipLaunchKernelGGL((k_step<M, P, true, false>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
-                               static_cast<const S*>(src), static_cast<S*>(dst), kp,
-                               static_cast<S*>(mom_out));
-        } else if (kp.hold_lo + kp.hold_hi > 0) {
-            hipLaunchKernelGGL((k_step<M, P, false, true>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
-                               static_cast<const S*>(src), static_cast<S*>(dst), kp,
-                               static_cast<S*>(nullptr));
-        } else {
-            hipLaunchKernelGGL((k_step<M, P, false, false>), grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
-                               static_cast<const S*>(src), static_cast<S*>(dst), kp,
-                               static_cast<S*>(nullptr));
-        }
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::init(const KParams& kp, const double* rho, const double* U,
+                                     const double* T, void* f, hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    return with_initial_form(kp, [&](auto F) {
+        hipLaunchKernelGGL((k_init<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                           dim3(kBlock), 0, s, rho, U, T, static_cast<typename P::S*>(f), kp);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_step_aa(ModelId m, Prec p, const KParams& kp, void* f, bool push,
-                          void* mom_out, hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        using S = typename P::S;
-        const dim3 grid(static_cast<unsigned>(step_blocks(m, p, kp)));
-        const auto go = [&](auto kernel) {
-            hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<S*>(f),
-                               kp, static_cast<S*>(mom_out));
-        };
-        const bool hold = kp.hold_lo + kp.hold_hi > 0;
-        if (push) {
-            if (mom_out && hold) go(k_step_aa<M, P, true, true, true>);
-            else if (mom_out) go(k_step_aa<M, P, true, false, true>);
-            else if (hold) go(k_step_aa<M, P, true, true, false>);
-            else go(k_step_aa<M, P, true, false, false>);
-        } else {
-            if (mom_out && hold) go(k_step_aa<M, P, false, true, true>);
-            else if (mom_out) go(k_step_aa<M, P, false, false, true>);
-            else if (hold) go(k_step_aa<M, P, false, true, false>);
-            else go(k_step_aa<M, P, false, false, false>);
-        }
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::set_pop(const KParams& kp, const double* fin, void* f,
+                                        hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    return with_initial_form(kp, [&](auto F) {
+        hipLaunchKernelGGL((k_set_pop<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                           dim3(kBlock), 0, s, fin, static_cast<typename P::S*>(f), kp);
         return hipGetLastError();
     });
 }
 
-hipError_t launch_to_ab(ModelId m, Prec p, const KParams& kp, const void* f, void* out,
-                        hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        using S = typename P::S;
-        return with_form(kp, [&](auto F) {
-            hipLaunchKernelGGL((k_to_ab<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
-                               dim3(kBlock), 0, s, static_cast<const S*>(f), static_cast<S*>(out),
-                               kp);
-            return hipGetLastError();
-        });
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::get_pop(const KParams& kp, const void* f, double* fout,
+                                        hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    return with_form(kp, [&](auto F) {
+        hipLaunchKernelGGL((k_get_pop<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                           dim3(kBlock), 0, s, static_cast<const typename P::S*>(f), fout, kp);
+        return hipGetLastError();
     });
 }
 
-hipError_t launch_from_ab(ModelId m, Prec p, const KParams& kp, const void* f, void* out,
-                          hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        using S = typename P::S;
-        return with_initial_form(kp, [&](auto F) {
-            hipLaunchKernelGGL((k_from_ab<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
-                               dim3(kBlock), 0, s, static_cast<const S*>(f), static_cast<S*>(out),
-                               kp);
-            return hipGetLastError();
-        });
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::step(const KParams& kp, const void* src, void* dst,
+                                     void* mom_out, hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    using S = typename P::S;
+    const dim3 grid(static_cast<unsigned>(step_blocks(M::id, PR, kp)));
+    const auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
+                           static_cast<const S*>(src), static_cast<S*>(dst), kp,
+                           static_cast<S*>(mom_out));
+    };
+    const bool hold = kp.hold_lo + kp.hold_hi > 0;
+    if (mom_out && !dst) {
+        if (hold) go(k_step<M, P, true, true, false>);
+        else go(k_step<M, P, true, false, false>);
+    } else if (mom_out) {
+        if (hold) go(k_step<M, P, true, true>);
+        else go(k_step<M, P, true, false>);
+    } else {
+        if (hold) go(k_step<M, P, false, true>);
+        else go(k_step<M, P, false, false>);
+    }
+    return hipGetLastError();
+}
+
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::step_aa(const KParams& kp, void* f, bool push, void* mom_out,
+                                        hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    using S = typename P::S;
+    const dim3 grid(static_cast<unsigned>(step_blocks(M::id, PR, kp)));
+    const auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<S*>(f), kp,
+                           static_cast<S*>(mom_out));
+    };
+    const bool hold = kp.hold_lo + kp.hold_hi > 0;
+    if (push) {
+        if (mom_out && hold) go(k_step_aa<M, P, true, true, true>);
+        else if (mom_out) go(k_step_aa<M, P, true, false, true>);
+        else if (hold) go(k_step_aa<M, P, true, true, false>);
+        else go(k_step_aa<M, P, true, false, false>);
+    } else {
+        if (mom_out && hold) go(k_step_aa<M, P, false, true, true>);
+        else if (mom_out) go(k_step_aa<M, P, false, false, true>);
+        else if (hold) go(k_step_aa<M, P, false, true, false>);
+        else go(k_step_aa<M, P, false, false, false>);
+    }
+    return hipGetLastError();
+}
+
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::to_ab(const KParams& kp, const void* f, void* out,
+                                      hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    using S = typename P::S;
+    return with_form(kp, [&](auto F) {
+        hipLaunchKernelGGL((k_to_ab<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                           dim3(kBlock), 0, s, static_cast<const S*>(f), static_cast<S*>(out), kp);
+        return hipGetLastError();
     });
 }
 
-hipError_t launch_moments(ModelId m, Prec p, const KParams& kp, const void* f, double* rho,
-                          double* U, double* T, hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        return with_form(kp, [&](auto F) {
-            hipLaunchKernelGGL((k_moments<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
-                               dim3(kBlock), 0, s, static_cast<const typename P::S*>(f), rho, U,
-                               T, kp);
-            return hipGetLastError();
-        });
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::from_ab(const KParams& kp, const void* f, void* out,
+                                        hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    using S = typename P::S;
+    return with_initial_form(kp, [&](auto F) {
+        hipLaunchKernelGGL((k_from_ab<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                           dim3(kBlock), 0, s, static_cast<const S*>(f), static_cast<S*>(out), kp);
+        return hipGetLastError();
     });
 }
 
-hipError_t launch_conservation(ModelId m, Prec p, const KParams& kp, const void* f,
-                               double* partials, double* out, hipStream_t s) {
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::moments(const KParams& kp, const void* f, double* rho, double* U,
+                                        double* T, hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    return with_form(kp, [&](auto F) {
+        hipLaunchKernelGGL((k_moments<M, P, decltype(F)::value>), dim3(cell_blocks(kp.N)),
+                           dim3(kBlock), 0, s, static_cast<const typename P::S*>(f), rho, U, T, kp);
+        return hipGetLastError();
+    });
+}
+
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::conservation(const KParams& kp, const void* f, double* partials,
+                                             hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
     const int nb = reduce_blocks(kp.N);
-    const int D = (m == ModelId::D2Q33) ? 2 : 3;
-    hipError_t e = with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        return with_form(kp, [&](auto F) {
-            hipLaunchKernelGGL((k_conservation<M, P, decltype(F)::value>), dim3(nb), dim3(kBlock),
-                               0, s, static_cast<const typename P::S*>(f), kp, partials);
-            return hipGetLastError();
-        });
+    return with_form(kp, [&](auto F) {
+        hipLaunchKernelGGL((k_conservation<M, P, decltype(F)::value>), dim3(nb), dim3(kBlock), 0,
+                           s, static_cast<const typename P::S*>(f), kp, partials);
+        return hipGetLastError();
     });
-    if (e != hipSuccess) return e;
-    return launch_sum_partials(partials, nb, D + 2, D + 2, out, s);
 }
 
-hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_fill_zero, dim3(cell_blocks(n)), dim3(kBlock), 0, s, p, n);
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::lambda_init(const KParams& kp, const void* fn,
+                                            const double* dLdrho, void* lam, double* partK,
+                                            hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    using S = typename P::S;
+    hipLaunchKernelGGL((k_lambda_init<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s,
+                       static_cast<const S*>(fn), dLdrho, static_cast<S*>(lam), kp, partK);
     return hipGetLastError();
 }
 
-hipError_t launch_sum_partials(const double* part, long long n, int stride, int count,
-                               double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, part, n, stride, count, out);
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::adjoint_step(const KParams& kp, const void* lam_src,
+                                             void* lam_dst, const void* mom, double* partA,
+                                             const void* mark_state, double* partM,
+                                             hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    using S = typename P::S;
+    const long long blocks = step_blocks(M::id, PR, kp);
+    const auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kp.bx), 0, s,
+                           static_cast<const S*>(lam_src), static_cast<S*>(lam_dst),
+                           static_cast<const S*>(mom), kp, partA,
+                           static_cast<const S*>(mark_state), partM);
+    };
+    const bool hold = kp.hold_lo + kp.hold_hi > 0;
+    if (mom) {
+        // (the omega marks are not taken with held planes)
+        if (hold) go(k_adjoint<M, P, true, false, true>);
+        else if (mark_state) go(k_adjoint<M, P, true, true, false>);
+        else go(k_adjoint<M, P, true, false, false>);
+    } else {
+        if (mark_state) go(k_adjoint<M, P, false, true, false>);
+        else go(k_adjoint<M, P, false, false, false>);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_lambda_init(ModelId m, Prec p, const KParams& kp, const void* fn,
-                              const double* dLdrho, void* lam, double* partK, hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        using S = typename P::S;
-        hipLaunchKernelGGL((k_lambda_init<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s,
-                           static_cast<const S*>(fn), dLdrho, static_cast<S*>(lam), kp, partK);
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_adjoint_step(ModelId m, Prec p, const KParams& kp, const void* lam_src,
-                               void* lam_dst, const void* mom, double* partA,
-                               const void* mark_state, double* partM, hipStream_t s) {
-    const long long blocks = step_blocks(m, p, kp);
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        using S = typename P::S;
-        const auto go = [&](auto kernel) {
-            hipLaunchKernelGGL(kernel, dim3(static_cast<unsigned>(blocks)), dim3(kp.bx), 0, s,
-                               static_cast<const S*>(lam_src), static_cast<S*>(lam_dst),
-                               static_cast<const S*>(mom), kp, partA,
-                               static_cast<const S*>(mark_state), partM);
-        };
-        const bool hold = kp.hold_lo + kp.hold_hi > 0;
-        if (mom) {
-            // (the omega marks are not taken with held planes)
-            if (hold) go(k_adjoint<M, P, true, false, true>);
-            else if (mark_state) go(k_adjoint<M, P, true, true, false>);
-            else go(k_adjoint<M, P, true, false, false>);
-        } else {
-            if (mark_state) go(k_adjoint<M, P, false, true, false>);
-            else go(k_adjoint<M, P, false, false, false>);
-        }
-        return hipGetLastError();
-    });
-}
-
-hipError_t launch_dT_init(ModelId m, Prec p, const KParams& kp, const void* lam0,
-                          const double* rho, const double* U, const double* T, double* dT,
-                          hipStream_t s) {
-    return with_types(m, p, [&](auto M_, auto P_) {
-        using M = decltype(M_);
-        using P = decltype(P_);
-        hipLaunchKernelGGL((k_dT_init<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s,
-                           static_cast<const typename P::S*>(lam0), rho, U, T, dT, kp);
-        return hipGetLastError();
-    });
+template <class M, Prec PR>
+hipError_t ModelKernels<M, PR>::dT_init(const KParams& kp, const void* lam0, const double* rho,
+                                        const double* U, const double* T, double* dT,
+                                        hipStream_t s) {
+    using P = typename PrecOf<PR>::type;
+    hipLaunchKernelGGL((k_dT_init<M, P>), dim3(cell_blocks(kp.N)), dim3(kBlock), 0, s,
+                       static_cast<const typename P::S*>(lam0), rho, U, T, dT, kp);
+    return hipGetLastError();
 }
 
 }  // namespace lbm

@@ -1,6 +1,8 @@
 // lbm_model.h - compile-time velocity sets of the 2D 33-velocity (Table 2) and
-// 3D 95-velocity (Table 3) on-lattice models, shared by the host validation
-// code and the HIP kernels of this library.
+// 3D 95-velocity (Table 3) on-lattice models of 4th-order accuracy, and of
+// the lower-order 3D 19- and 15-velocity sets the paper says the same
+// construction yields (paragraph after Formula (10)), shared by the host
+// validation code and the HIP kernels of this library.
 //
 // A model is a list of symmetry groups, each given by an integer
 // representative; the group is the orbit of the representative under
@@ -14,7 +16,7 @@
 
 namespace lbm {
 
-enum class ModelId : int { D2Q33 = 0, D3Q95 = 1 };
+enum class ModelId : int { D2Q33 = 0, D3Q95 = 1, D3Q19 = 2, D3Q15 = 3 };
 enum class Prec : int { F64 = 0, F32S = 1 };
 
 struct GroupRep {
@@ -38,6 +40,13 @@ inline constexpr double kD3Q95PrintedW[10] = {.206847, .00442257, .0333341, .012
                                               .00264319, .000927908, .00106078, .000804376,
                                               .00274697};
 inline constexpr double kD3Q95PrintedC = .421803;
+
+// Lower-order 3D sets (order of accuracy m = 2: Formula (5) up to n_max = 4,
+// Omega(2, 3) = 4 equations for three group weights and c, Formula (10)).
+// The paper names them without tables; their weights are solved on the host
+// from a generic start (least squares at c = 1, then Newton).
+inline constexpr GroupRep kD3Q19Reps[3] = {{1, {0, 0, 0}}, {6, {1, 0, 0}}, {12, {1, 1, 0}}};
+inline constexpr GroupRep kD3Q15Reps[3] = {{1, {0, 0, 0}}, {6, {1, 0, 0}}, {8, {1, 1, 1}}};
 
 template <int D_, int Q_, int G_>
 struct VelocityTable {
@@ -148,21 +157,39 @@ constexpr VelocityTable<D, Q, G> make_table(const GroupRep (&reps)[G]) {
 
 inline constexpr auto kD2Q33 = make_table<2, 33, 8>(kD2Q33Reps);
 inline constexpr auto kD3Q95 = make_table<3, 95, 10>(kD3Q95Reps);
+inline constexpr auto kD3Q19 = make_table<3, 19, 3>(kD3Q19Reps);
+inline constexpr auto kD3Q15 = make_table<3, 15, 3>(kD3Q15Reps);
 static_assert(kD2Q33.ok && kD3Q95.ok, "orbit sizes must match Tables 2 and 3");
+static_assert(kD3Q19.ok && kD3Q15.ok, "orbit sizes of the lower-order sets");
 static_assert(kD2Q33.emax == 4 && kD3Q95.emax == 5, "largest displacement");
+static_assert(kD3Q19.emax == 1 && kD3Q15.emax == 1, "largest displacement");
 
 // Largest displacement over the supported models: halo width of the gather.
 inline constexpr int kMaxDisp = 5;
 inline constexpr int kMaxG = 10;
 
-// Model tags used as template parameters of the kernels.
+// Model tags used as template parameters of the kernels.  m is the order of
+// accuracy (Formula (5) up to n_max = 2m), N the order of the Hermite
+// equilibrium, N = m (the paragraph after Formula (5) asks for N >= m).
 struct D2Q33 {
-    static constexpr int D = 2, Q = 33, G = 8;
+    static constexpr int D = 2, Q = 33, G = 8, m = 4, N = 4;
+    static constexpr ModelId id = ModelId::D2Q33;
     static constexpr const auto& table = kD2Q33;
 };
 struct D3Q95 {
-    static constexpr int D = 3, Q = 95, G = 10;
+    static constexpr int D = 3, Q = 95, G = 10, m = 4, N = 4;
+    static constexpr ModelId id = ModelId::D3Q95;
     static constexpr const auto& table = kD3Q95;
+};
+struct D3Q19 {
+    static constexpr int D = 3, Q = 19, G = 3, m = 2, N = 2;
+    static constexpr ModelId id = ModelId::D3Q19;
+    static constexpr const auto& table = kD3Q19;
+};
+struct D3Q15 {
+    static constexpr int D = 3, Q = 15, G = 3, m = 2, N = 2;
+    static constexpr ModelId id = ModelId::D3Q15;
+    static constexpr const auto& table = kD3Q15;
 };
 
 }  // namespace lbm

@@ -20,18 +20,30 @@
 namespace lbm {
 namespace {
 
+// A compiled model: its velocity table, its order of accuracy m (Formula (5)
+// up to n_max = 2m) and the start of the weight solve (the printed table
+// values; none for the lower-order sets, which start from least squares).
 struct ModelView {
-    int D, Q, G;
+    int D, Q, G, m;
     const int (*e)[3];
     const int* group;
+    const int* e2;
     const double* printedW;
     double printedC;
 };
 
+template <class M>
+ModelView view_of(const double* printedW, double printedC) {
+    return {M::D, M::Q, M::G, M::m, M::table.e, M::table.group, M::table.e2, printedW, printedC};
+}
+
 ModelView view(ModelId m) {
-    if (m == ModelId::D2Q33)
-        return {2, 33, 8, kD2Q33.e, kD2Q33.group, kD2Q33PrintedW, kD2Q33PrintedC};
-    return {3, 95, 10, kD3Q95.e, kD3Q95.group, kD3Q95PrintedW, kD3Q95PrintedC};
+    switch (m) {
+        case ModelId::D2Q33: return view_of<D2Q33>(kD2Q33PrintedW, kD2Q33PrintedC);
+        case ModelId::D3Q19: return view_of<D3Q19>(nullptr, 1.0);
+        case ModelId::D3Q15: return view_of<D3Q15>(nullptr, 1.0);
+        default: return view_of<D3Q95>(kD3Q95PrintedW, kD3Q95PrintedC);
+    }
 }
 
 // Exponent tuples (a_1 >= ... >= a_D, all even) of the equations of Formula (5)
@@ -161,7 +173,7 @@ System build_system(const OrbitModel& om, int m) {
     return s;
 }
 
-System build_system(ModelId m) { return build_system(builtin_model(m), 4); }
+System build_system(ModelId m) { return build_system(builtin_model(m), view(m).m); }
 
 void residual_and_jacobian(const System& s, const std::vector<double>& W, double c,
                            std::vector<double>& F, std::vector<std::vector<double>>* J) {
@@ -256,16 +268,41 @@ bool newton(const System& s, std::vector<quad>& x, std::string& err) {
     return false;
 }
 
+// Least-squares group weights at the speed x[G]: (A^T A) W = A^T rhs with
+// A = c^|a| B; written into x[0 .. G).
+bool least_squares_weights(const System& s, std::vector<quad>& x, std::string& err) {
+    const int n = static_cast<int>(s.rhs.size());
+    const int G = s.G;
+    std::vector<std::vector<quad>> A(n, std::vector<quad>(G));
+    for (int k = 0; k < n; ++k) {
+        quad cp = 1;
+        for (int p = 0; p < s.order[k]; ++p) cp *= x[G];
+        for (int g = 0; g < G; ++g) A[k][g] = cp * static_cast<quad>(s.B[k][g]);
+    }
+    std::vector<std::vector<quad>> N(G, std::vector<quad>(G + 1, 0));
+    for (int i = 0; i < G; ++i) {
+        for (int j = 0; j < G; ++j)
+            for (int k = 0; k < n; ++k) N[i][j] += A[k][i] * A[k][j];
+        for (int k = 0; k < n; ++k) N[i][G] += A[k][i] * static_cast<quad>(s.rhs[k]);
+    }
+    std::vector<quad> w0;
+    if (!solve_dense(N, w0)) {
+        err = "singular least-squares system for the initial weights";
+        return false;
+    }
+    for (int g = 0; g < G; ++g) x[g] = w0[g];
+    return true;
+}
+
 }  // namespace
 
 bool model_from_shape(int D, int Q, ModelId& m) {
-    if (D == 2 && Q == 33) {
-        m = ModelId::D2Q33;
-        return true;
-    }
-    if (D == 3 && Q == 95) {
-        m = ModelId::D3Q95;
-        return true;
+    for (ModelId id : {ModelId::D2Q33, ModelId::D3Q95, ModelId::D3Q19, ModelId::D3Q15}) {
+        const ModelView v = view(id);
+        if (v.D == D && v.Q == Q) {
+            m = id;
+            return true;
+        }
     }
     return false;
 }
@@ -275,9 +312,8 @@ int model_q(ModelId m) { return view(m).Q; }
 int model_groups(ModelId m) { return view(m).G; }
 int model_group_of(ModelId m, int i) { return view(m).group[i]; }
 int model_e(ModelId m, int i, int k) { return view(m).e[i][k]; }
-int model_e2(ModelId m, int g) {
-    return m == ModelId::D2Q33 ? kD2Q33.e2[g] : kD3Q95.e2[g];
-}
+int model_e2(ModelId m, int g) { return view(m).e2[g]; }
+int model_order(ModelId m) { return view(m).m; }
 
 bool model_matches(ModelId m, const int32_t* e) {
     const ModelView v = view(m);
@@ -300,8 +336,12 @@ bool model_solve(ModelId m, double* W, double* c, std::string& err) {
         return false;
     }
     std::vector<quad> x(v.G + 1);
-    for (int g = 0; g < v.G; ++g) x[g] = v.printedW[g];
     x[v.G] = v.printedC;
+    if (v.printedW) {
+        for (int g = 0; g < v.G; ++g) x[g] = v.printedW[g];
+    } else if (!least_squares_weights(s, x, err)) {
+        return false;
+    }
     if (!newton(s, x, err)) return false;
     for (int g = 0; g < v.G; ++g) W[g] = static_cast<double>(x[g]);
     *c = static_cast<double>(x[v.G]);
@@ -329,26 +369,8 @@ bool model_build(int D, int m, int G, const int32_t* reps, const double* w_guess
     x[G] = c_guess;
     if (w_guess) {
         for (int g = 0; g < G; ++g) x[g] = w_guess[g];
-    } else {
-        // least-squares weights at c_guess: (A^T A) W = A^T rhs, A = c^|a| B
-        std::vector<std::vector<quad>> A(n, std::vector<quad>(G));
-        for (int k = 0; k < n; ++k) {
-            quad cp = 1;
-            for (int p = 0; p < s.order[k]; ++p) cp *= x[G];
-            for (int g = 0; g < G; ++g) A[k][g] = cp * static_cast<quad>(s.B[k][g]);
-        }
-        std::vector<std::vector<quad>> N(G, std::vector<quad>(G + 1, 0));
-        for (int i = 0; i < G; ++i) {
-            for (int j = 0; j < G; ++j)
-                for (int k = 0; k < n; ++k) N[i][j] += A[k][i] * A[k][j];
-            for (int k = 0; k < n; ++k) N[i][G] += A[k][i] * static_cast<quad>(s.rhs[k]);
-        }
-        std::vector<quad> w0;
-        if (!solve_dense(N, w0)) {
-            err = "singular least-squares system for the initial weights";
-            return false;
-        }
-        for (int g = 0; g < G; ++g) x[g] = w0[g];
+    } else if (!least_squares_weights(s, x, err)) {
+        return false;
     }
     if (!newton(s, x, err)) return false;
     out.D = D;

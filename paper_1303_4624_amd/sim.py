@@ -12,7 +12,9 @@ import torch
 
 from . import _lib as L
 
-MODELS = {"D2Q33": (2, 33), "D3Q95": (3, 95)}
+# The 4th-order models of Tables 2 and 3, and the lower-order (m = 2) 3D
+# 19- and 15-velocity sets built by the same construction.
+MODELS = {"D2Q33": (2, 33), "D3Q95": (3, 95), "D3Q19": (3, 19), "D3Q15": (3, 15)}
 PRECISIONS = {"fp64": L.LBM_FP64, "fp32s": L.LBM_FP32_SHIFTED}
 STREAMING = {"ab": L.LBM_STREAM_AB, "aa": L.LBM_STREAM_AA}
 
@@ -29,7 +31,7 @@ def _dev_bytes(nbytes: int, device) -> torch.Tensor:
 class Simulation:
     """One periodic lattice with a supported velocity set.
 
-    model     : "D2Q33" or "D3Q95"
+    model     : "D2Q33", "D3Q95" (4th order), "D3Q19" or "D3Q15" (2nd order)
     extent    : (nx, ny[, nz])
     omega     : relaxation frequency
     precision : "fp64" or "fp32s" (float32 deviations from w_i rho0)
@@ -79,34 +81,52 @@ class Simulation:
             raise ValueError(f"field has {t.numel()} values, expected {want[0]}")
         return t
 
+    # -- stream ordering ------------------------------------------------
+    # The library runs on self.stream; tensors are made and consumed on the
+    # caller's current stream.  Each call first makes self.stream wait for
+    # the current stream (inputs written there), then the current stream
+    # wait for self.stream (outputs read there), and records every tensor
+    # handed to the library on self.stream so that the caching allocator does
+    # not reuse its memory while a kernel may still use it.
+    def _call(self, fn, *args, tensors=()):
+        cur = torch.cuda.current_stream(self.device)
+        other = cur.cuda_stream != self.stream.cuda_stream
+        if other:
+            self.stream.wait_stream(cur)
+        res = fn(*args)
+        if other:
+            for t in tensors:
+                if isinstance(t, torch.Tensor) and t.is_cuda:
+                    t.record_stream(self.stream)
+            cur.wait_stream(self.stream)
+        return res
+
     # -- C ABI wrappers -------------------------------------------------
     def init_fields(self, rho, U, T) -> None:
         r, u, t = self._field(rho), self._field(U, self.D), self._field(T)
-        self._keep = (r, u, t)   # alive until the stream has consumed them
-        L.lbm_init_fields(self.ctx, r, u, t)
+        self._call(L.lbm_init_fields, self.ctx, r, u, t, tensors=(r, u, t))
 
     def set_populations(self, f) -> None:
         t = self._field(f, self.Q)
-        self._keep = (t,)
-        L.lbm_set_populations(self.ctx, t)
+        self._call(L.lbm_set_populations, self.ctx, t, tensors=(t,))
 
     def get_populations(self) -> torch.Tensor:
         out = torch.empty((self.Q,) + self.grid_shape, dtype=torch.float64, device=self.device)
-        L.lbm_get_populations(self.ctx, out)
+        self._call(L.lbm_get_populations, self.ctx, out, tensors=(out,))
         return out
 
     def step(self, n: int = 1) -> None:
-        L.lbm_step(self.ctx, n)
+        self._call(L.lbm_step, self.ctx, n)
 
     def moments(self):
         rho = torch.empty(self.grid_shape, dtype=torch.float64, device=self.device)
         U = torch.empty((self.D,) + self.grid_shape, dtype=torch.float64, device=self.device)
         T = torch.empty(self.grid_shape, dtype=torch.float64, device=self.device)
-        L.lbm_moments(self.ctx, rho, U, T)
+        self._call(L.lbm_moments, self.ctx, rho, U, T, tensors=(rho, U, T))
         return rho, U, T
 
     def conservation(self) -> np.ndarray:
-        return L.lbm_conservation(self.ctx, self.D)
+        return self._call(L.lbm_conservation, self.ctx, self.D)
 
     def set_fixed_planes(self, n_lo: int, n_hi: int, state_lo=None, state_hi=None) -> None:
         """Hold the first n_lo / last n_hi planes of the slowest axis at
@@ -118,7 +138,8 @@ class Simulation:
 
     def set_graph_steps(self, steps: int) -> None:
         """Replay step() in HIP graphs of `steps` (even) steps; 0 turns it off.
-        Needs a non-default stream (pass ``stream=torch.cuda.Stream()``)."""
+        Needs a non-default stream (pass ``stream=torch.cuda.Stream()``; the
+        calls order themselves against the caller's current stream)."""
         L.lbm_set_graph_steps(self.ctx, steps)
 
     def set_omega(self, omega: float) -> None:
@@ -130,14 +151,15 @@ class Simulation:
         keep their step moments (keep >= ceil(n/k): no recomputation later)."""
         nb = L.lbm_checkpoint_bytes(self.ctx, n, k, keep)
         ck = _dev_bytes(nb, self.device)
-        L.lbm_run_checkpointed(self.ctx, n, k, keep, ck, nb)
+        self._call(L.lbm_run_checkpointed, self.ctx, n, k, keep, ck, nb, tensors=(ck,))
         return ck
 
     def restore_checkpoint(self, n: int, k: int, ckpt: torch.Tensor, slot: int,
                            keep: int = 1) -> None:
         """Continue from snapshot `slot` of run_checkpointed(n, k, keep) (the
         state at t = slot*k; slot = ceil(n/k): the final state)."""
-        L.lbm_restore_checkpoint(self.ctx, n, k, keep, ckpt, ckpt.numel() * 8, slot)
+        self._call(L.lbm_restore_checkpoint, self.ctx, n, k, keep, ckpt, ckpt.numel() * 8, slot,
+                   tensors=(ckpt,))
 
     def adjoint(self, n: int, k: int, ckpt: torch.Tensor, rho_init, U_init, T_init,
                 dL_drho_final, want_T: bool = True, want_omega: bool = True,
@@ -149,9 +171,8 @@ class Simulation:
         r, u, t = self._field(rho_init), self._field(U_init, self.D), self._field(T_init)
         g = self._field(dL_drho_final)
         dT = torch.empty(self.grid_shape, dtype=torch.float64, device=self.device) if want_T else None
-        dw = L.lbm_adjoint(self.ctx, n, k, keep, ckpt, ckpt.numel() * 8, r, u, t, g, workspace,
-                           wsb, dT, want_omega)
-        self._keep = (r, u, t, g, workspace)
+        dw = self._call(L.lbm_adjoint, self.ctx, n, k, keep, ckpt, ckpt.numel() * 8, r, u, t, g,
+                        workspace, wsb, dT, want_omega, tensors=(ckpt, r, u, t, g, workspace, dT))
         return dT, dw
 
     def close(self) -> None:

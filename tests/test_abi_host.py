@@ -54,6 +54,31 @@ def test_velocity_set_matches_tables_and_oracle(name):
     assert abs(w.sum() - 1) < 1e-14
 
 
+@pytest.mark.parametrize("name,D,Q", [("D3Q19", 3, 19), ("D3Q15", 3, 15)])
+def test_lower_order_sets_match_oracle_and_are_accepted(name, D, Q):
+    # The lower-order sets (order m = 2) the construction also gives: the
+    # library solves them from least squares at c = 1; both sides round the
+    # exact root, the closed-form D3Q19 / D3Q15 weights.
+    e, w, c = L.lbm_velocity_set(D, Q)
+    ov = ovs.velocity_set(name)
+    assert np.array_equal(e, ov.e.astype(np.int32))
+    assert c == ov.c and np.array_equal(w, ov.w)
+    # the same set from the general constructor, at m = 2
+    reps = np.array([r for (_o, r) in ovs.LOWER_ORDER[name]], dtype=np.int32)
+    be, _bg, bw, bc, _res = L.lbm_model_build(D, 2, reps, 1.0)
+    assert np.array_equal(be, e) and bc == c and np.array_equal(bw, w)
+    a = dict(D=D, Q=Q, e=e, w=w, c=c, extent=[8, 6, 4], omega=1.2, precision=L.LBM_FP64,
+             rho0=1.0, stream=0)
+    assert _create_status(**a) == L.LBM_OK
+    assert _create_status(**dict(a, precision=L.LBM_FP32_SHIFTED)) == L.LBM_OK
+    # Formula (5) is checked up to order 2m = 4: a wrong speed is refused
+    assert _create_status(**dict(a, c=c * 1.001)) == L.LBM_E_INVALID
+    wb = w.copy()
+    wb[ov.group == 1] *= 1.001
+    wb[0] = 1 - wb[1:].sum()
+    assert _create_status(**dict(a, w=wb)) == L.LBM_E_INVALID
+
+
 def test_velocity_set_unsupported():
     with pytest.raises(L.LBMError) as ex:
         L.lbm_velocity_set(3, 27)

@@ -105,3 +105,33 @@ def test_graph_replay_around_checkpointed_runs_and_restores(streaming):
         finally:
             plain.close()
             graph.close()
+
+
+@pytest.mark.parametrize("streaming", ["ab", "aa"])
+def test_side_stream_without_making_it_current(streaming):
+    # A Simulation on its own stream, driven from code whose current stream
+    # is the default one: inputs made on the current stream are waited for,
+    # outputs are ready on it, and the results equal a default-stream run.
+    from paper_1303_4624_amd import Simulation
+    extent = (40, 12, 10)
+    rho, U, th = smooth_ic(extent, seeds=(7, 8, 9, 10, 11), amp_u=0.03)
+    ref = Simulation("D3Q95", extent, 1.4, precision="fp32s", streaming=streaming)
+    ref.init_fields(rho, U, th * ref.T0)
+    ref.step(9)
+    want = [x.cpu() for x in ref.moments()]
+    ref.close()
+    side = torch.cuda.Stream()
+    sim = Simulation("D3Q95", extent, 1.4, precision="fp32s", stream=side, streaming=streaming)
+    for _ in range(3):
+        sim.init_fields(rho, U, th * sim.T0)
+        sim.step(9)
+        got = [x.cpu() for x in sim.moments()]
+        assert all(torch.equal(a, b) for a, b in zip(got, want))
+        # checkpoints and a restore on the side stream, read back on the default one
+        ck = sim.run_checkpointed(6, 3)
+        sim.restore_checkpoint(6, 3, ck, 1)
+        sim.step(3)
+        r1 = sim.moments()[0].cpu()
+        sim.restore_checkpoint(6, 3, ck, 2)
+        assert torch.equal(r1, sim.moments()[0].cpu())
+    sim.close()
