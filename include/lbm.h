@@ -279,6 +279,24 @@ int lbm_moments(lbm_ctx* ctx, double* rho, double* U, double* T);
 int lbm_conservation(lbm_ctx* ctx, double* out);
 
 /*
+ * lbm_conservation_noalloc - lbm_conservation for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and the same sums, bit
+ * for bit, but the reduction partials and the reduced values live in a static
+ * device array of the library (41.5 KB, one per GPU, kept until the process
+ * ends) instead of the scratch buffer given to lbm_bind.  No device memory is
+ * allocated or freed; the first call on a GPU looks up that GPU's array.
+ * Every grid the library accepts fits (at most 1024 partials of D + 2
+ * values); a grid that needed more would be refused with LBM_E_INVALID.
+ * Calls on one GPU share the array: calls that overlap in time on one GPU
+ * (from several host threads, or on several streams before the previous
+ * call returned) race; each call overwrites every element it reads, so
+ * consecutive calls need no clearing.  Synchronises the stream, like
+ * lbm_conservation.
+ */
+int lbm_conservation_noalloc(lbm_ctx* ctx, double* out);
+
+/*
  * lbm_set_fixed_planes - the shock-tube end conditions of the experiment in
  * the results section: the first n_lo and the last n_hi planes along the
  * slowest axis (the XY-planes at the two ends of z in 3D, the X-rows at the

@@ -599,15 +599,16 @@ LBM_API int lbm_moments(lbm_ctx* ctx, double* rho, double* U, double* T) {
     return LBM_OK;
 }
 
-LBM_API int lbm_conservation(lbm_ctx* ctx, double* out) {
-    int rc;
-    if ((rc = require_init(ctx)) != LBM_OK) return rc;
-    if (!out) return fail(ctx, LBM_E_INVALID, "out is NULL");
-    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+namespace {
+
+// The conservation sums with the reduction partials at `scratch` (room for
+// reduce_blocks(N) * (D + 2) partials, rounded up to 256 bytes, then D + 2
+// results).  The caller has checked the context and made its device current.
+int conservation_into(lbm_ctx* ctx, void* scratch, double* out) {
     const int K = ctx->D + 2;
-    double* partials = static_cast<double*>(ctx->scratch);
+    double* partials = static_cast<double*>(scratch);
     const size_t parts = round_up(static_cast<size_t>(lbm::reduce_blocks(ctx->N)) * K * 8);
-    double* dres = reinterpret_cast<double*>(static_cast<char*>(ctx->scratch) + parts);
+    double* dres = reinterpret_cast<double*>(static_cast<char*>(scratch) + parts);
     hipError_t e = lbm::launch_conservation(ctx->model, ctx->prec, ctx->kp, ctx->f[ctx->cur],
                                             partials, dres, ctx->stream);
     if (e != hipSuccess) return fail_hip(ctx, e, "conservation kernels");
@@ -641,6 +642,34 @@ LBM_API int lbm_conservation(lbm_ctx* ctx, double* out) {
     }
     if (!finite) return fail(ctx, LBM_E_NONFINITE, "a conservation sum is not finite");
     return LBM_OK;
+}
+
+}  // namespace
+
+LBM_API int lbm_conservation(lbm_ctx* ctx, double* out) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    if (!out) return fail(ctx, LBM_E_INVALID, "out is NULL");
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    return conservation_into(ctx, ctx->scratch, out);
+}
+
+LBM_API int lbm_conservation_noalloc(lbm_ctx* ctx, double* out) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    if (!out) return fail(ctx, LBM_E_INVALID, "out is NULL");
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    void* scratch = nullptr;
+    size_t cap = 0;
+    hipError_t e = lbm::static_scratch(ctx->device, &scratch, &cap);
+    if (e != hipSuccess) return fail_hip(ctx, e, "address of the static scratch array");
+    const size_t need = scratch_bytes(ctx);
+    if (need > cap)
+        return fail(ctx, LBM_E_INVALID,
+                    "the grid needs " + std::to_string(need) +
+                        " bytes of reduction scratch, the static array holds " +
+                        std::to_string(cap));
+    return conservation_into(ctx, scratch, out);
 }
 
 LBM_API int lbm_set_streaming(lbm_ctx* ctx, int scheme) {

@@ -163,6 +163,12 @@ hipError_t launch_dT_init(ModelId m, Prec p, const KParams& kp, const void* lam0
 hipError_t launch_sum_partials(const double* part, long long n, int stride, int count,
                                double* out, hipStream_t s);
 
+// The library's static device scratch array (a file-scope __device__ array,
+// one copy per GPU, kept until the process ends): its device address on
+// `device`, which must be the current device, resolved once per device, and
+// its size in bytes.  Used only by lbm_conservation_noalloc.
+hipError_t static_scratch(int device, void** ptr, size_t* bytes);
+
 // Sizes used by the API layer for its buffers.
 long long step_blocks(ModelId m, Prec p, const KParams& kp);
 

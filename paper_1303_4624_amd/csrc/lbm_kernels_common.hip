@@ -4,12 +4,23 @@
 // launchers instantiated in the lbm_kernels_<model>.hip translation units.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "lbm_internal.h"
 
 namespace lbm {
+
+// Scratch of lbm_conservation_noalloc: the per-block partials of the
+// conservation sums (at most 1024 blocks of D + 2 <= 5 float64 values,
+// rounded up to 256 bytes) and the D + 2 reduced sums.  Every element a call
+// reads is written earlier in that call, so nothing needs clearing.
+constexpr size_t kStaticScratchDoubles = 1024 * 5 + 64;
+static __device__ __align__(256) double scratch[kStaticScratchDoubles];
+
 namespace {
 
 constexpr int kCommonBlock = 256;
+constexpr int kMaxDevices = 64;
 
 __global__ __launch_bounds__(kCommonBlock) void k_fill_zero(double* p, long long n) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -122,6 +133,24 @@ hipError_t launch_dT_init(ModelId m, Prec p, const KParams& kp, const void* lam0
                           const double* rho, const double* U, const double* T, double* dT,
                           hipStream_t s) {
     return LBM_DISPATCH(dT_init(kp, lam0, rho, U, T, dT, s));
+}
+
+hipError_t static_scratch(int device, void** ptr, size_t* bytes) {
+    // In host code `scratch` names a host-side stand-in; the device address
+    // of each GPU's copy comes from hipGetSymbolAddress with that GPU current.
+    static std::mutex mu;
+    static void* addr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    *bytes = sizeof(scratch);
+    return hipSuccess;
 }
 
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {

@@ -148,6 +148,8 @@ void check_create() {
     EXPECT(lbm_moments(ctx, nullptr, nullptr, nullptr) == LBM_E_STATE);
     double cons[5];
     EXPECT(lbm_conservation(ctx, cons) == LBM_E_STATE);
+    EXPECT(lbm_conservation_noalloc(ctx, cons) == LBM_E_STATE);
+    EXPECT(lbm_conservation_noalloc(nullptr, cons) == LBM_E_INVALID);
     EXPECT(lbm_init_fields(ctx, nullptr, nullptr, nullptr) == LBM_E_STATE);
     EXPECT(lbm_restore_checkpoint(ctx, 10, 3, 1, nullptr, 0, 0) == LBM_E_STATE);
     // host memory is not device memory (and there is no device here)

@@ -44,5 +44,6 @@ hipError_t launch_dT_init(ModelId, Prec, const KParams&, const void*, const doub
 hipError_t launch_sum_partials(const double*, long long, int, int, double*, hipStream_t) {
     return hipErrorNoDevice;
 }
+hipError_t static_scratch(int, void**, size_t*) { return hipErrorNoDevice; }
 
 }  // namespace lbm
