@@ -297,6 +297,20 @@ int lbm_conservation(lbm_ctx* ctx, double* out);
 int lbm_conservation_noalloc(lbm_ctx* ctx, double* out);
 
 /*
+ * lbm_stream_copy - measurement reference, not part of the method: copies the
+ * current populations (LBM_STREAM_AB) into the other bound buffer n times
+ * with a plain streaming kernel (one 16-byte vector per lane, non-temporal
+ * stores), i.e. the bytes of one update step (each population read once and
+ * written once) without its gather and arithmetic, on the same buffers: the
+ * read + write rate HBM sustains for this state, against which the step's
+ * rate is compared.  The state is not changed (the other buffer is the next
+ * step's destination anyway).  Asynchronous.  LBM_E_STATE before
+ * lbm_init_fields, LBM_E_UNSUPPORTED with LBM_STREAM_AA (one buffer),
+ * LBM_E_INVALID for n < 0.
+ */
+int lbm_stream_copy(lbm_ctx* ctx, int n);
+
+/*
  * lbm_set_fixed_planes - the shock-tube end conditions of the experiment in
  * the results section: the first n_lo and the last n_hi planes along the
  * slowest axis (the XY-planes at the two ends of z in 3D, the X-rows at the

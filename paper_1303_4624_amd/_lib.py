@@ -32,7 +32,7 @@ LBM_MAX_Q = 95
 EXPORTED = [
     "lbm_velocity_set", "lbm_equation_count", "lbm_model_build", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
     "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments",
-    "lbm_conservation", "lbm_conservation_noalloc", "lbm_set_fixed_planes", "lbm_set_streaming", "lbm_set_graph_steps",
+    "lbm_conservation", "lbm_conservation_noalloc", "lbm_stream_copy", "lbm_set_fixed_planes", "lbm_set_streaming", "lbm_set_graph_steps",
     "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed", "lbm_restore_checkpoint",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_str",
     "lbm_last_error",
@@ -70,6 +70,7 @@ _SIGS = {
     "lbm_moments": (_c.c_int, [_vp, _vp, _vp, _vp]),
     "lbm_conservation": (_c.c_int, [_vp, _pd]),
     "lbm_conservation_noalloc": (_c.c_int, [_vp, _pd]),
+    "lbm_stream_copy": (_c.c_int, [_vp, _c.c_int]),
     "lbm_set_fixed_planes": (_c.c_int, [_vp, _c.c_int, _c.c_int, _pd, _pd]),
     "lbm_set_streaming": (_c.c_int, [_vp, _c.c_int]),
     "lbm_set_graph_steps": (_c.c_int, [_vp, _c.c_int]),
@@ -221,6 +222,10 @@ def lbm_conservation(ctx, D: int) -> np.ndarray:
     out = np.zeros(D + 2, dtype=np.float64)
     _check(library().lbm_conservation(ctx, out.ctypes.data_as(_pd)), "lbm_conservation", ctx)
     return out
+
+
+def lbm_stream_copy(ctx, n: int) -> None:
+    _check(library().lbm_stream_copy(ctx, int(n)), "lbm_stream_copy", ctx)
 
 
 def lbm_conservation_noalloc(ctx, D: int) -> np.ndarray:

@@ -672,6 +672,22 @@ LBM_API int lbm_conservation_noalloc(lbm_ctx* ctx, double* out) {
     return conservation_into(ctx, scratch, out);
 }
 
+LBM_API int lbm_stream_copy(lbm_ctx* ctx, int n) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    if (n < 0) return fail(ctx, LBM_E_INVALID, "n must be >= 0");
+    if (ctx->aa)
+        return fail(ctx, LBM_E_UNSUPPORTED, "the copy needs the two buffers of LBM_STREAM_AB");
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    const size_t bytes = pop_bytes(ctx);
+    for (int r = 0; r < n; ++r) {
+        const hipError_t e = lbm::launch_stream_copy(ctx->f[ctx->cur], ctx->f[1 - ctx->cur], bytes,
+                                                     ctx->stream);
+        if (e != hipSuccess) return fail_hip(ctx, e, "copy kernel");
+    }
+    return LBM_OK;
+}
+
 LBM_API int lbm_set_streaming(lbm_ctx* ctx, int scheme) {
     if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
     if (scheme != LBM_STREAM_AB && scheme != LBM_STREAM_AA)

@@ -149,6 +149,8 @@ hipError_t launch_moments(ModelId m, Prec p, const KParams& kp, const void* f, d
 hipError_t launch_conservation(ModelId m, Prec p, const KParams& kp, const void* f,
                                double* partials, double* out, hipStream_t s);
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s);
+// Streaming copy of `bytes` (a multiple of 4; src and dst 16-byte aligned).
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 hipError_t launch_lambda_init(ModelId m, Prec p, const KParams& kp, const void* fn,
                               const double* dLdrho, void* lam, double* partK, hipStream_t s);
 // mom == nullptr: transposed streaming only (no collision, partA unused).

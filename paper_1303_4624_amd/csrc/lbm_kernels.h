@@ -63,12 +63,12 @@ namespace {
 #ifndef LBM_ADJ_SCHED_BARRIER
 #define LBM_ADJ_SCHED_BARRIER 0
 #endif
-// Occupancy target of the FP32-shifted adjoint kernel (waves per SIMD).  It
-// needs about 190 VGPRs (the 95 gathered adjoint values, float64 group sums,
-// the per-cell equilibrium polynomials); a target of 3 waves (168 VGPRs)
-// makes it spill to scratch memory.
+// Occupancy target of the FP32-shifted adjoint kernel (waves per SIMD): 3
+// waves (<= 168 VGPRs) fit without scratch when its loads are issued in
+// velocity order (LBM_ADJ_GATHER_SORTED 0); sorted by source row they need
+// about 180 VGPRs, which fit 2 waves only.
 #ifndef LBM_ADJ_WAVES
-#define LBM_ADJ_WAVES 2
+#define LBM_ADJ_WAVES 3
 #endif
 #ifndef LBM_F32_WAVES
 #define LBM_F32_WAVES 1
@@ -325,11 +325,13 @@ __device__ __forceinline__ void store_pop(char* p, S val) {
 // Gather v_i = src_i(x - SIGN*e_i) with periodic wrap on every axis.
 // Order in which a gather issues its loads: the velocity order, or sorted
 // by source slab, then source row (LBM_ADJ_GATHER_SORTED, transposed gather).
-// Measured: the adjoint on D3Q95 FP32-shifted 128^3 1.3 % faster sorted; the
-// forward pull sorted lost 0.5 % at 384^3 (and gained 1.5 % at 256^3), so it
-// keeps the velocity order.  The order changes no value, only the issue order.
+// The order changes no value, only the issue order.  Measured on D3Q95
+// FP32-shifted: the forward pull sorted lost 0.5 % at 384^3, so it keeps the
+// velocity order; the adjoint sorted needs ~180 VGPRs (2 waves per SIMD) and
+// in velocity order fits 3 waves, which is 2 % faster at 128^3 (the adjoint
+// of 200 steps with recomputation: 117.2 against 119.6 ms, interleaved).
 #ifndef LBM_ADJ_GATHER_SORTED
-#define LBM_ADJ_GATHER_SORTED 1
+#define LBM_ADJ_GATHER_SORTED 0
 #endif
 template <class M, bool SORTED>
 struct LoadOrder {
@@ -979,53 +981,45 @@ __global__ __launch_bounds__(kBlock) void k_lambda_init(const typename P::S* __r
     block_sum<1>(acc, partK + blockIdx.x, false);
 }
 
-// Derivative coefficients of P = 1 + h with respect to s, u2 and d, per group.
+// Coefficients of h and of its derivatives with respect to s, u2 and d for
+// one group, straight from (u2, d, X) (the adjoint kernels: per-cell
+// polynomials in X, as the forward kernels use, would hold a dozen more
+// float64 values through their group loop and push them past 3 waves per
+// SIMD).  With K1 = (X - D)/2, K2 = (D + 2 - X)/4,
+// K3 = (X^2 - 2(D + 2)X + D(D + 2))/8 (the file header's a0, a1, a2) and
 //   N = 4: P_s  = a1 + s (2 a2 + s (1/2 + s/6))
-//          P_u2 = b0 + s (-1/2 - s/4),     b0 = -1/2 + u2/4 + d (D + 2 - X)/4
-//          P_d  = c0 + s (c1 + s c2),       c0 = (X - D)/2 + (D + 2 - X) u2/4
-//                                                + d (X^2 - 2 (D + 2) X + D (D + 2))/4
-//                                           c1 = (X - D - 2)/2, c2 = (X - D - 4)/4
+//          P_u2 = b0 + s (-1/2 - s/4),   b0 = -1/2 + u2/4 + d K2
+//          P_d  = c0 + s (c1 + s c2),     c0 = K1 + u2 K2 + 2 d K3,
+//                                         c1 = (X - D - 2)/2, c2 = (X - D - 4)/4
 //   N = 2: P_s = 1 + s, P_u2 = -1/2, P_d = (X - D)/2.
-// Per cell they are polynomials in X (XDer), per group only X_g enters.
 struct GDer {
     double b0, c0, c1, c2;
 };
 template <int D, int N>
-struct XDer {
-    double b00, b01, c00, c01, c02;
-    __device__ __forceinline__ XDer(double u2, double d) {
-        constexpr double Dd = D;
-        if constexpr (N == 4) {
-            b00 = -0.5 + 0.25 * u2 + d * (0.25 * (Dd + 2.0));
-            b01 = -0.25 * d;
-            c00 = -0.5 * Dd + u2 * (0.25 * (Dd + 2.0)) + d * (0.25 * Dd * (Dd + 2.0));
-            c01 = 0.5 - 0.25 * u2 - d * (0.5 * (Dd + 2.0));
-            c02 = 0.25 * d;
-        } else {
-            static_assert(N == 2, "equilibrium order 2 or 4");
-            b00 = -0.5;
-            b01 = 0.0;
-            c00 = -0.5 * Dd;
-            c01 = 0.5;
-            c02 = 0.0;
-        }
+__device__ __forceinline__ void group_coef_der(double u2, double d, double X, GCoef& gc,
+                                               GDer& gd) {
+    constexpr double Dd = D;
+    if constexpr (N == 4) {
+        const double k1 = 0.5 * (X - Dd), k2 = 0.25 * (Dd + 2.0 - X);
+        const double k3 = 0.125 * (X * X - 2.0 * (Dd + 2.0) * X + Dd * (Dd + 2.0));
+        gc.a0 = -0.5 * u2 + 0.125 * u2 * u2 + d * (k1 + u2 * k2 + d * k3);
+        gc.a1 = 1.0 - 0.5 * u2 + d * (0.5 * (X - Dd - 2.0));
+        gc.a2 = 0.5 - 0.25 * u2 + d * (0.25 * (X - Dd - 4.0));
+        gd.b0 = -0.5 + 0.25 * u2 + d * k2;
+        gd.c0 = k1 + u2 * k2 + 2.0 * d * k3;
+        gd.c1 = 0.5 * (X - Dd - 2.0);
+        gd.c2 = 0.25 * (X - Dd - 4.0);
+    } else {
+        static_assert(N == 2, "equilibrium order 2 or 4");
+        gc.a0 = 0.5 * (-u2 + d * (X - Dd));
+        gc.a1 = 1.0;
+        gc.a2 = 0.5;
+        gd.b0 = -0.5;
+        gd.c0 = 0.5 * (X - Dd);
+        gd.c1 = 0.0;
+        gd.c2 = 0.0;
     }
-    __device__ __forceinline__ GDer at(double X) const {
-        GDer c;
-        if constexpr (N == 4) {
-            c.b0 = b00 + b01 * X;
-            c.c0 = c00 + X * (c01 + X * c02);
-            c.c1 = 0.5 * X - 0.5 * (D + 2.0);
-            c.c2 = 0.25 * X - 0.25 * (D + 4.0);
-        } else {
-            c.b0 = -0.5;
-            c.c0 = c00 + X * c01;
-            c.c1 = 0.0;
-            c.c2 = 0.0;
-        }
-        return c;
-    }
-};
+}
 
 // P_s, P_u2, P_d of order N from the group's coefficients.
 template <int N, class R>
@@ -1121,13 +1115,11 @@ void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict
     // slightly different model than the forward step and bias the omega
     // gradient, which relies on <lambda^t, f*^t> staying constant.
     double s0 = 0.0, su2 = 0.0, sd = 0.0, ssx = 0.0, ssy = 0.0, ssz = 0.0;
-    const XPoly<D, M::N> xp(u2, d);
-    const XDer<D, M::N> xd(u2, d);
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        const double X = group_x<M, g>(k);
-        const GCoef gc = xp.at(X);
-        const GDer gd = xd.at(X);
+        GCoef gc;
+        GDer gd;
+        group_coef_der<D, M::N>(u2, d, group_x<M, g>(k), gc, gd);
         const R a0 = R(gc.a0), a1 = R(gc.a1), a2 = R(gc.a2), a2x2 = R(2.0 * gc.a2);
         const R b0 = R(gd.b0), c0 = R(gd.c0), c1 = R(gd.c1), c2 = R(gd.c2);
         // sum mu P = sum mu + sum mu h with P = 1 + h: the O(1) part is summed in
@@ -1240,11 +1232,12 @@ __global__ __launch_bounds__(kBlock) void k_dT_init(const typename P::S* __restr
     const double u2 = (ux * ux + uy * uy + uz * uz) * k.invT0;
     const double utx = ux * k.invT0, uty = uy * k.invT0, utz = uz * k.invT0;
     const PopAt<M, kFormAB> pa(k, c);
-    const XDer<D, M::N> xd(u2, d);
     double sd = 0.0;
     static_for<G>([&](auto GI) {
         constexpr int g = decltype(GI)::value;
-        const GDer gd = xd.at(group_x<M, g>(k));
+        GCoef gc;
+        GDer gd;
+        group_coef_der<D, M::N>(u2, d, group_x<M, g>(k), gc, gd);
         double tg = 0.0;
         static_for<M::table.gsize[g]>([&](auto JI) {
             constexpr int i = M::table.gstart[g] + decltype(JI)::value;

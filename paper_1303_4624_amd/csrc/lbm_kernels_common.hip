@@ -46,6 +46,21 @@ __global__ __launch_bounds__(kCommonBlock) void k_sum_partials(const double* __r
     }
 }
 
+// Streaming copy: one 16-byte vector per lane, plain load, non-temporal
+// store (the step's own choices); the last bytes % 16 as 4-byte words.
+typedef float v4f __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kCommonBlock) void k_stream_copy(const v4f* __restrict__ src,
+                                                              v4f* __restrict__ dst,
+                                                              long long n16, int tail4) {
+    const long long i = static_cast<long long>(blockIdx.x) * kCommonBlock + threadIdx.x;
+    if (i < n16) __builtin_nontemporal_store(src[i], &dst[i]);
+    if (blockIdx.x == 0 && static_cast<int>(threadIdx.x) < tail4) {
+        const float* s4 = reinterpret_cast<const float*>(src + n16);
+        float* d4 = reinterpret_cast<float*>(dst + n16);
+        d4[threadIdx.x] = s4[threadIdx.x];
+    }
+}
+
 // Calls f with a model tag and the precision as template arguments.
 template <class F>
 hipError_t with_model(ModelId m, Prec p, F&& f) {
@@ -151,6 +166,16 @@ hipError_t static_scratch(int device, void** ptr, size_t* bytes) {
     *ptr = addr[device];
     *bytes = sizeof(scratch);
     return hipSuccess;
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    const long long n16 = static_cast<long long>(bytes / 16);
+    const int tail4 = static_cast<int>((bytes % 16) / 4);
+    const long long blocks = (n16 + kCommonBlock - 1) / kCommonBlock;
+    hipLaunchKernelGGL(k_stream_copy, dim3(static_cast<unsigned>(blocks > 0 ? blocks : 1)),
+                       dim3(kCommonBlock), 0, s, static_cast<const v4f*>(src),
+                       static_cast<v4f*>(dst), n16, tail4);
+    return hipGetLastError();
 }
 
 hipError_t launch_fill_zero(double* p, long long n, hipStream_t s) {

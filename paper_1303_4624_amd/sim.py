@@ -128,6 +128,12 @@ class Simulation:
     def conservation(self) -> np.ndarray:
         return self._call(L.lbm_conservation, self.ctx, self.D)
 
+    def stream_copy(self, n: int = 1) -> None:
+        """Measurement reference: n plain streaming copies of the state into
+        the other population buffer (the bytes of a step, no gather or
+        arithmetic); the state is unchanged."""
+        self._call(L.lbm_stream_copy, self.ctx, n)
+
     def set_fixed_planes(self, n_lo: int, n_hi: int, state_lo=None, state_hi=None) -> None:
         """Hold the first n_lo / last n_hi planes of the slowest axis at
         f^eq(state) after every step; a state is (rho, U_x, U_y[, U_z], T)."""

@@ -45,5 +45,6 @@ hipError_t launch_sum_partials(const double*, long long, int, int, double*, hipS
     return hipErrorNoDevice;
 }
 hipError_t static_scratch(int, void**, size_t*) { return hipErrorNoDevice; }
+hipError_t launch_stream_copy(const void*, void*, size_t, hipStream_t) { return hipErrorNoDevice; }
 
 }  // namespace lbm

@@ -175,9 +175,11 @@ def test_conservation_sums_match_oracle_and_are_conserved(precision):
     assert np.array_equal(c1, c1b)                 # fixed-order reduction
     drift = np.abs(c1 - c0) / scale
     _say("drift", drift)
-    # FP32: per-step rounding of float32 values; on the uniform plateaus of
-    # the Riemann problem every cell rounds alike, so it adds up linearly.
-    assert np.all(drift <= (1e-13 if precision == "fp64" else 2.5e-8 * w.steps))
+    # FP32-shifted: the stored values are float32, but the moment sums of a
+    # cell are float64, so the plateaus of the Riemann problem no longer
+    # drift coherently; measured over these 400 steps: mass 3.6e-7, energy
+    # 4.6e-7, momentum 0 (the problem is symmetric).  Bar: 1e-6.
+    assert np.all(drift <= (1e-13 if precision == "fp64" else 1e-6))
 
 
 def test_errors_are_reported_not_faulted():
@@ -294,3 +296,29 @@ def test_full_size_sampled_cells_match_oracle(model, extent, precision, tol):
         worst = max(worst, e)
     _say("worst sampled error", worst)
     assert worst <= tol
+
+
+def test_stream_copy_reference_leaves_the_state():
+    # lbm_stream_copy (the bandwidth reference the bench compares the step
+    # with) copies the state into the other buffer and changes nothing the
+    # update sees; in-place streaming has no second buffer.
+    from paper_1303_4624_amd import Simulation, _lib as L
+    extent = (70, 9, 6)
+    rho, U, th = smooth_ic(extent, seeds=(1, 2, 3, 4, 5), amp_u=0.03)
+    runs = []
+    for copies in (0, 3):
+        sim = new_sim("D3Q95", extent, 1.3, "fp32s")
+        sim.init_fields(rho, U, th * sim.T0)
+        sim.step(2)
+        sim.stream_copy(copies)
+        f = sim.get_populations().cpu()
+        sim.step(3)
+        runs.append((f, sim.get_populations().cpu()))
+        sim.close()
+    assert torch.equal(runs[0][0], runs[1][0]) and torch.equal(runs[0][1], runs[1][1])
+    aa = Simulation("D3Q95", extent, 1.3, precision="fp32s", streaming="aa")
+    aa.init_fields(rho, U, th * aa.T0)
+    with pytest.raises(L.LBMError) as ex:
+        aa.stream_copy(1)
+    assert ex.value.status == L.LBM_E_UNSUPPORTED
+    aa.close()
