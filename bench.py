@@ -361,6 +361,97 @@ def cpu_oracle_adjoint_baseline(extent=(32, 32, 32), steps=12):
                       f"sum (rho_n - rho*)^2 w.r.t. T_init and omega ({dt:.1f} s)"}
 
 
+def _read_counters(path):
+    """rocprofv3 counter CSV -> list of dicts, one per (dispatch, counter)."""
+    import csv
+    with open(path) as fh:
+        return list(csv.DictReader(fh))
+
+
+def summarize_profiles(prof_dir: str, grid: int = 384) -> str:
+    """Text summary of the rocprofv3 runs of the headline command (kernel
+    stats, FETCH_SIZE and WRITE_SIZE passes, an L2 pass) under prof_dir;
+    also writes the traffic record the bench reads (TRAFFIC_FILE) when the
+    counter passes are present.  Needs no GPU."""
+    import csv
+    N = grid ** 3
+    alg = 2 * 95 * 4 * N
+    lines = []
+    stats = os.path.join(prof_dir, "kt", "kt_kernel_stats.csv")
+    avg = {}
+    if os.path.exists(stats):
+        with open(stats) as fh:
+            for r in csv.DictReader(fh):
+                avg[r["Name"]] = (int(r["Calls"]), float(r["AverageNs"]), float(r["MinNs"]))
+        lines.append("kernel statistics (rocprofv3 --kernel-trace --stats):")
+        for name in ("k_step", "k_stream_copy"):
+            if name in avg:
+                calls, a, mn = avg[name]
+                lines.append(f"  {name:14s} {calls:3d} launches, average {a / 1e6:.4f} ms "
+                             f"(min {mn / 1e6:.4f}) -> {alg / a:.1f} GB/s = {alg / a / 8000:.4f} "
+                             f"of 8 TB/s")
+        if "k_step" in avg and "k_stream_copy" in avg:
+            lines.append(f"  k_step at {avg['k_stream_copy'][1] / avg['k_step'][1]:.4f} of the "
+                         "streaming copy of the same bytes on the same buffers")
+            lines.append(f"  k_step: {N / (avg['k_step'][1] / 1e9) / 1e6:.1f} MLUPS")
+    scales, per = {}, {}
+    for ctr, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        path = os.path.join(prof_dir, sub, f"{sub}_counter_collection.csv")
+        if not os.path.exists(path):
+            continue
+        rows = [r for r in _read_counters(path) if r["Counter_Name"] == ctr]
+        cal = [float(r["Counter_Value"]) for r in rows
+               if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer")
+               and int(r["Grid_Size"]) == 131072]
+        if not cal:
+            continue
+        scales[ctr] = (1 << 31) / (cal[0] * 1024)
+        for name in ("k_step", "k_stream_copy"):
+            v = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"] == name]
+            if v:
+                per[(name, ctr)] = (len(v), sum(v) / len(v) * 1024 * scales[ctr])
+    if scales:
+        lines.append("")
+        lines.append("HBM counters, one rocprofv3 --pmc pass per counter, each scaled by what "
+                     "it reads for a 2 GiB device copy (__amd_rocclr_copyBuffer) in the same run:")
+        for ctr, sc in scales.items():
+            lines.append(f"  {ctr} scale {sc:.4f}")
+        for name in ("k_step", "k_stream_copy"):
+            if (name, "FETCH_SIZE") in per and (name, "WRITE_SIZE") in per:
+                n, rd = per[(name, "FETCH_SIZE")]
+                _, wr = per[(name, "WRITE_SIZE")]
+                lines.append(f"  {name:14s} {n:3d} launches: read {rd / 1e9:.3f} GB, write "
+                             f"{wr / 1e9:.3f} GB per launch = {(rd + wr) / alg:.4f} x the "
+                             f"algorithmic {alg / 1e9:.3f} GB ({rd / N:.1f} + {wr / N:.1f} B/cell)")
+        if ("k_step", "FETCH_SIZE") in per and ("k_step", "WRITE_SIZE") in per:
+            rd, wr = per[("k_step", "FETCH_SIZE")][1], per[("k_step", "WRITE_SIZE")][1]
+            rec = {"kernel": "k_step<D3Q95, FP32-shifted> (stream + collide)",
+                   "grid": [grid] * 3, "kernel_source_sha256_16": kernel_source_hash(),
+                   "bytes_per_launch": int(rd + wr), "read_bytes_per_launch": int(rd),
+                   "write_bytes_per_launch": int(wr), "algorithmic_bytes_per_launch": alg,
+                   "fetch_scale": round(scales["FETCH_SIZE"], 4),
+                   "write_scale": round(scales["WRITE_SIZE"], 4),
+                   "avg_kernel_ns": avg.get("k_step", (0, 0.0, 0))[1]}
+            with open(TRAFFIC_FILE, "w") as fh:
+                json.dump(rec, fh, indent=1)
+    l2 = os.path.join(prof_dir, "l2", "l2_counter_collection.csv")
+    if os.path.exists(l2):
+        rows = [r for r in _read_counters(l2) if r["Kernel_Name"] in ("k_step", "k_stream_copy")]
+        lines.append("")
+        lines.append("L2 (TCC) counters per cell update, mean over launches:")
+        for name in ("k_step", "k_stream_copy"):
+            tot = {}
+            for r in rows:
+                if r["Kernel_Name"] == name:
+                    tot.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            if tot:
+                txt = ", ".join(f"{c} {sum(v) / len(v) / N:.3f}" for c, v in sorted(tot.items()))
+                lines.append(f"  {name:14s} {txt}")
+        lines.append("  (TCC_EA0_RDREQ: 128-byte reads from memory; TCC_EA0_WRREQ: 64-byte "
+                     "writes; 380 B per cell each way = 2.97 reads, 5.94 writes)")
+    return "\n".join(lines)
+
+
 # Side measurements after the headline (all by default; --only picks some).
 SECTIONS = ("256c", "d2q33", "aa", "tubes", "adjoint")
 
@@ -378,7 +469,13 @@ def main():
     ap.add_argument("--only", default="",
                     help="comma-separated side measurements to run (default: all of them): "
                          + ",".join(SECTIONS))
+    ap.add_argument("--summarize-profiles", metavar="DIR", default="",
+                    help="print the summary of rocprofv3 runs of the headline command in DIR "
+                         "(kt/, fetch/, write/, l2/) and update the traffic record; no GPU")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        print(summarize_profiles(args.summarize_profiles, args.grid))
+        return
     only = set(x for x in args.only.split(",") if x)
     if only - set(SECTIONS):
         ap.error(f"unknown sections {sorted(only - set(SECTIONS))}")
