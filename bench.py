@@ -136,6 +136,29 @@ def run_fp64_and_error(extent, omega, steps_time, steps_err, model="D3Q95", step
     return out, (errs[0] if len(errs) == 1 else errs)
 
 
+def run_model(model, extent, precision, steps, omega=1.8):
+    """Throughput of another velocity set through the same kernel template
+    (the lower-order D3Q19/D3Q15 sets): MLUPS and the fraction of 8 TB/s at
+    2 Q b bytes per cell update."""
+    import torch
+    from paper_1303_4624_amd import Simulation
+    from synth_inputs import smooth_ic
+    rho, U, th = smooth_ic(extent)
+    sim = Simulation(model, extent, omega, precision=precision)
+    sim.init_fields(rho, U, th * sim.T0)
+    del rho, U, th
+    wall, ev = timed_steps(sim, steps, 4)
+    N, Q = sim.N, sim.Q
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    b = 8 if precision == "fp64" else 4
+    mlups = N * steps / ev / 1e6
+    return {"grid": list(extent), "steps": steps, "mlups": round(mlups, 2),
+            "ms_per_step": round(ev / steps * 1e3, 4), "bytes_per_cell": 2 * Q * b,
+            "roofline_frac": round(mlups * 2 * Q * b / 1e3 / HBM_PEAK_GBS, 4)}
+
+
 def run_aa(extent, steps, tile=None):
     """D3Q95 FP32-shifted with in-place (AA) streaming: one population buffer."""
     import torch
@@ -453,7 +476,7 @@ def summarize_profiles(prof_dir: str, grid: int = 384) -> str:
 
 
 # Side measurements after the headline (all by default; --only picks some).
-SECTIONS = ("256c", "d2q33", "aa", "tubes", "adjoint")
+SECTIONS = ("256c", "d2q33", "lower", "aa", "tubes", "adjoint")
 
 
 def main():
@@ -563,6 +586,11 @@ def main():
             d["roofline_frac"] = round(d["mlups"] * bpc / 1e3 / HBM_PEAK_GBS, 4)
             out[f"d2q33_{prec}_8192sq"] = d
         out["d2q33_fp32s_vs_fp64_8192sq"] = err
+    if not args.no_extras and want("lower"):
+        log("[bench] lower-order D3Q19 / D3Q15 on 384^3")
+        for model in ("D3Q19", "D3Q15"):
+            for prec in ("fp32s", "fp64"):
+                out[f"{model.lower()}_{prec}_384c"] = run_model(model, extent, prec, 100)
     if not args.no_extras and want("aa"):
         log("[bench] in-place (AA) streaming, 384^3 and 768^3")
         out["aa_fp32s_384c"] = run_aa((384, 384, 384), 100)

@@ -193,3 +193,99 @@ def test_held_planes_clear_to_periodic():
     finally:
         sim.close()
         ref.close()
+
+
+def _crossing(z, y, level, from_right=True):
+    """Position where y crosses `level`, linearly interpolated (scanning from
+    the right end when from_right)."""
+    idx = range(len(y) - 2, -1, -1) if from_right else range(len(y) - 1)
+    for i in idx:
+        a, b = y[i] - level, y[i + 1] - level
+        if a == 0:
+            return float(z[i])
+        if a * b < 0:
+            return float(z[i] + (z[i + 1] - z[i]) * a / (a - b))
+    return float("nan")
+
+
+@pytest.mark.parametrize("wname,plateaus", [
+    ("d3q95_11x11x800_tube", ((300, 480), (540, 700))),
+    ("d2q33_11x800_tube", ((340, 390), (470, 580))),
+])
+def test_paper_tube_axis_profiles_against_exact_solution(wname, plateaus):
+    # The experiment's comparison (the shock-tube paragraph and the caption of
+    # its figure): density and temperature along the tube's central axis
+    # against the analytical Riemann solution.  Writes the profiles beside the
+    # exact ones (gpurun_out/figure1_<workload>.csv and a summary), and bounds
+    # the plateau deviations and the front positions.
+    import os
+    w = WORKLOADS[wname]
+    D = len(w.extent)
+    (lr, lt), (rr, rt) = tube_states(w)
+    nh = int(w.extra["hold"])
+    rho, U, th = workload_ic(w)
+    prof = {}
+    for precision in ("fp64", "fp32s"):
+        def hold(T0):
+            return (nh, nh, _state(lr, lt, T0, D), _state(rr, rt, T0, D))
+        r, u, t, T0, _ = _gpu(w.model, w.extent, w.omega, rho, U, th, w.steps, hold, precision)
+        axis = (slice(None),) + tuple(n // 2 for n in w.extent[:-1])[::-1]
+        prof[precision] = (r[axis], t[axis] / T0, u[(D - 1,) + axis])
+    L_ = w.extent[-1]
+    z = np.arange(L_, dtype=np.float64)
+    z0 = L_ // 2 - 0.5                 # the initial interface lies between planes L/2 - 1 and L/2
+    g = orm.monatomic_gamma(D)
+    left, right = (lr, 0.0, lr * lt * T0), (rr, 0.0, rr * rt * T0)
+    er, eu, ep = orm.sample(left, right, g, (z - z0) / w.steps)
+    eth = ep / er / T0
+    st = orm.star_state(left, right, g)
+    lh, lt_, rt_, rh = orm.wave_speeds(left, right, g)
+    r64, th64, u64 = prof["fp64"]
+    (a, b), (c, d) = plateaus
+    dev = {"rho_L*": r64[a:b].mean() / st.rho_l - 1, "rho_R*": r64[c:d].mean() / st.rho_r - 1,
+           "theta_L*": th64[a:b].mean() / (st.p / st.rho_l / T0) - 1,
+           "theta_R*": th64[c:d].mean() / (st.p / st.rho_r / T0) - 1}
+    # where the density crosses a level, measured and in the exact profile
+    # (sampled 100 times finer); a shock or the contact crosses at its
+    # discontinuity, the fan at the given fraction of its density drop
+    zf = np.linspace(0, L_ - 1, 100 * (L_ - 1) + 1)
+    erf = orm.sample(left, right, g, (zf - z0) / w.steps)[0]
+    fan = lambda q: lr - q * (lr - st.rho_l)
+    levels = {"shock": (0.5 * (st.rho_r + rr), True), "contact": (0.5 * (st.rho_l + st.rho_r), True),
+              "fan 2 %": (fan(0.02), False), "fan 50 %": (fan(0.5), False),
+              "fan 98 %": (fan(0.98), False)}
+    fronts = {k_: (_crossing(z, r64, lev, fr), _crossing(zf, erf, lev, fr))
+              for k_, (lev, fr) in levels.items()}
+    assert abs(fronts["shock"][1] - (z0 + rh * w.steps)) < 0.02
+    assert abs(fronts["contact"][1] - (z0 + st.u * w.steps)) < 0.02
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    os.makedirs(out, exist_ok=True)
+    with open(os.path.join(out, f"figure1_{wname}.csv"), "w") as fh:
+        fh.write("z,rho_fp64,theta_fp64,u_fp64,rho_fp32s,theta_fp32s,rho_exact,theta_exact,u_exact\n")
+        r32, th32, _ = prof["fp32s"]
+        for i in range(L_):
+            fh.write(f"{i},{r64[i]:.10g},{th64[i]:.10g},{u64[i]:.10g},{r32[i]:.10g},"
+                     f"{th32[i]:.10g},{er[i]:.10g},{eth[i]:.10g},{eu[i]:.10g}\n")
+    with open(os.path.join(out, f"figure1_{wname}_summary.txt"), "w") as fh:
+        fh.write(f"{wname}: {w.extent}, omega {w.omega}, t = {w.steps}, gamma {g:.6g}, "
+                 f"interface at z = {z0}\n")
+        fh.write("plateau means (FP64 GPU) against the exact solution:\n")
+        for k_, v_ in dev.items():
+            fh.write(f"  {k_:9s} {v_:+.3e}\n")
+        fh.write("density crossings (FP64 GPU) vs the exact profile, cells (shock, contact: half-way\n"
+                 "between the states they join; fan: the fraction of its density drop):\n")
+        for k_, (m_, x_) in fronts.items():
+            fh.write(f"  {k_:9s} measured {m_:8.2f} exact {x_:8.2f} diff {m_ - x_:+6.2f}\n")
+        fh.write(f"FP32-shifted vs FP64 on the axis: rho {np.abs(r32 - r64).max():.2e}, "
+                 f"theta {np.abs(th32 - th64).max():.2e}\n")
+    _say("plateau deviations", dev)
+    _say("fronts", fronts)
+    assert max(abs(x) for x in dev.values()) < 2e-3
+    # the fronts sit where the exact solution puts them; viscosity (nu =
+    # T0 (1/omega - 1/2)) only smears them, which moves the outer edges of the
+    # fan by about sqrt(nu t) ~ 8 cells, not its middle
+    assert abs(fronts["shock"][0] - fronts["shock"][1]) < 3
+    assert abs(fronts["contact"][0] - fronts["contact"][1]) < 3
+    assert abs(fronts["fan 50 %"][0] - fronts["fan 50 %"][1]) < 3
+    assert abs(fronts["fan 2 %"][0] - fronts["fan 2 %"][1]) < 15
+    assert abs(fronts["fan 98 %"][0] - fronts["fan 98 %"][1]) < 15
