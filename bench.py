@@ -97,6 +97,34 @@ def run_headline(extent, omega, steps, warmup):
     return wall, ev, ok, cons, copy_gbs
 
 
+def run_placement(extent, omega, trials, steps=20):
+    """The headline step and the streaming copy of the same bytes on `trials`
+    successive allocations of the population buffers: each trial frees the
+    previous simulation and allocates a new one behind a spacer of 0, 1 or
+    2 GiB, so the buffers land on other physical memory.  Returns per trial
+    the ms per step, the ms per copy and their ratio."""
+    import torch
+    from paper_1303_4624_amd import Simulation
+    from synth_inputs import smooth_ic
+    rho, U, th = smooth_ic(extent)
+    out = []
+    for t in range(trials):
+        spacer = torch.empty((t % 3) << 27, dtype=torch.float64, device="cuda")
+        sim = Simulation("D3Q95", extent, omega, precision="fp32s", rho0=1.0)
+        sim.init_fields(rho, U, th * sim.T0)
+        _, ev = timed_steps(sim, steps, 2)
+        gbs = copy_bandwidth(sim)
+        step_ms = ev / steps * 1e3
+        copy_ms = 2 * sim.pop_bytes / gbs / 1e6
+        sim.close()
+        del sim, spacer
+        torch.cuda.empty_cache()
+        out.append({"step_ms": round(step_ms, 4), "copy_ms": round(copy_ms, 4),
+                    "step_over_copy": round(step_ms / copy_ms, 4)})
+        log(f"[bench] placement trial {t}: step {step_ms:.3f} ms, copy {copy_ms:.3f} ms")
+    return out
+
+
 def run_fp64_and_error(extent, omega, steps_time, steps_err, model="D3Q95", steps_err_long=0):
     """FP64 and FP32-shifted throughput on `extent`, and the FP32-shifted vs
     FP64 GPU error after `steps_err` (and `steps_err_long`) steps from the
@@ -476,6 +504,225 @@ def summarize_profiles(prof_dir: str, grid: int = 384) -> str:
 
 
 # Side measurements after the headline (all by default; --only picks some).
+_MODEL_QD = {"D2Q33": (33, 2), "D3Q95": (95, 3), "D3Q19": (19, 3), "D3Q15": (15, 3)}
+# kernels launched one lane per cell over whole rows padded to 64 lanes
+_ROW_KERNELS = ("k_step", "k_step_aa", "k_adjoint")
+# kernels launched one lane per cell over ceil(N / 256) blocks of 256
+_FLAT_KERNELS = ("k_init", "k_moments", "k_to_ab", "k_from_ab", "k_set_pop", "k_get_pop",
+                 "k_lambda_init", "k_dT_init")
+
+
+def _instance(name: str):
+    """(kernel, model, precision, bool template flags) from a full rocprofv3
+    kernel name such as 'void lbm::(anonymous namespace)::k_step<lbm::D3Q95,
+    lbm::(anonymous namespace)::F32ST, false, false, true>(...)'."""
+    import re
+    m = re.search(r"(k_\w+)<([^>]*)>", name)
+    if not m:
+        m2 = re.search(r"(k_\w+)\(", name)
+        return (m2.group(1) if m2 else name.split("(")[0]), None, None, ()
+    args = [a.strip().replace("lbm::", "").replace("(anonymous namespace)::", "")
+            for a in m.group(2).split(",")]
+    model = args[0] if args and args[0] in _MODEL_QD else None
+    prec = {"F32ST": "F32S", "F64T": "F64"}.get(args[1]) if len(args) > 1 else None
+    flags = tuple(int(a == "true") for a in args[2:] if a in ("true", "false"))
+    return m.group(1), model, prec, flags
+
+
+def _alg_bytes_per_cell(kernel, model, prec, flags):
+    """Algorithmic HBM bytes per cell of one launch: each value the kernel
+    must read or write, once (storage b bytes per population or moment,
+    float64 fields and gradients 8 bytes)."""
+    if model is None or prec is None:
+        return None
+    Q, D = _MODEL_QD[model]
+    b = 8 if prec == "F64" else 4
+    mom = (D + 2) * b
+    if kernel == "k_step":                      # STORE_MOM, HOLD, POP
+        sm, _, pop = (flags + (0, 0, 1))[:3]
+        return Q * b + (Q * b if pop else 0) + (mom if sm else 0)
+    if kernel == "k_step_aa":                   # PUSH, HOLD, STORE_MOM
+        return 2 * Q * b + (mom if flags[2] else 0)
+    if kernel == "k_adjoint":                   # COLLIDE, MARK, HOLD
+        return 2 * Q * b + (mom if flags[0] else 0) + (Q * b if flags[1] else 0)
+    if kernel in ("k_to_ab", "k_from_ab"):
+        return 2 * Q * b
+    if kernel in ("k_init", "k_moments"):
+        return Q * b + 8 * (D + 2)
+    if kernel in ("k_set_pop", "k_get_pop"):
+        return Q * b + 8 * Q
+    if kernel == "k_conservation":
+        return Q * b
+    if kernel == "k_lambda_init":
+        return 2 * Q * b + 8
+    if kernel == "k_dT_init":
+        return Q * b + 8 * (D + 2) + 8
+    return None
+
+
+def _lane_cells():
+    """Launch lanes -> (cells, workload) for the grids the bench runs."""
+    from synth_inputs import WORKLOADS
+    shapes = {(384,) * 3: "384^3", (256,) * 3: "256^3", (8192, 8192): "8192^2",
+              (768,) * 3: "768^3", (128,) * 3: "128^3"}
+    for w in WORKLOADS.values():
+        if w.name.endswith("_tube"):
+            shapes[tuple(w.extent)] = "x".join(map(str, w.extent))
+    out = {}
+    for ext, label in shapes.items():
+        cells = 1
+        for n in ext:
+            cells *= n
+        rows = cells // ext[0]
+        out[("row", rows * (-(-ext[0] // 64) * 64))] = (cells, label)
+        out[("flat", -(-cells // 256) * 256)] = (cells, label)
+    return out
+
+
+def _walk_dispatches(rows, grid_of):
+    """Yield (row, instance, workload, cells, algorithmic bytes) for the
+    library's kernels in dispatch order; a grid-stride launch (the
+    conservation sums) and the streaming copy take the workload of the
+    launch before them."""
+    lanes = _lane_cells()
+    cur = (None, None)
+    for r in sorted(rows, key=lambda r: int(r["Dispatch_Id"])):
+        kernel, model, prec, flags = _instance(r["Kernel_Name"])
+        grid = grid_of(r)
+        if kernel in _ROW_KERNELS:
+            cells, label = lanes.get(("row", grid), (None, None))
+        elif kernel in _FLAT_KERNELS:
+            cells, label = lanes.get(("flat", grid), (None, None))
+        elif kernel in ("k_conservation", "k_stream_copy"):
+            cells, label = cur
+        else:
+            continue
+        if cells is None:
+            continue
+        if kernel in _ROW_KERNELS or kernel in _FLAT_KERNELS:
+            cur = (cells, label)
+        if kernel == "k_stream_copy":
+            inst, alg = kernel, 32 * grid           # one 16-byte vector per lane, each way
+        else:
+            inst = f"{kernel}<{model},{prec}" + "".join(f",{f}" for f in flags) + ">"
+            bpc = _alg_bytes_per_cell(kernel, model, prec, flags)
+            alg = bpc * cells if bpc else None
+        yield r, inst, label, cells, alg
+
+
+def summarize_all_kernels(prof_dir: str) -> str:
+    """Per-kernel-instance table of a rocprofv3 kernel trace (kt/) and of the
+    FETCH_SIZE / WRITE_SIZE passes (fetch/, write/) of a full bench run, all
+    taken without kernel-name truncation; needs no GPU."""
+    import csv
+    with open(os.path.join(prof_dir, "kt", "kt_kernel_trace.csv")) as fh:
+        trace = list(csv.DictReader(fh))
+    groups, other_ns = {}, 0.0
+    lib = set()
+    for r, inst, label, cells, alg in _walk_dispatches(
+            trace, lambda r: int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])):
+        lib.add(r["Dispatch_Id"])
+        key = (inst, label, int(r["Workgroup_Size_X"]), int(r["VGPR_Count"]))
+        g = groups.setdefault(key, {"ns": [], "alg": alg, "cells": cells})
+        g["ns"].append(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+    for r in trace:
+        if r["Dispatch_Id"] not in lib:
+            other_ns += float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+
+    # counters: mean per (instance, workload) over dispatches, scaled by what
+    # the counter reads for the 2 GiB device copy of the same pass
+    ctr, scales = {}, {}
+    for c, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        path = os.path.join(prof_dir, sub, f"{sub}_counter_collection.csv")
+        if not os.path.exists(path):
+            continue
+        rows = [r for r in _read_counters(path) if r["Counter_Name"] == c]
+        cal = [float(r["Counter_Value"]) for r in rows
+               if r["Kernel_Name"].startswith("__amd_rocclr_copyBuffer")
+               and int(r["Grid_Size"]) == 131072]
+        if not cal:
+            continue
+        scales[c] = (1 << 31) / (cal[0] * 1024)
+        for r, inst, label, cells, alg in _walk_dispatches(rows, lambda r: int(r["Grid_Size"])):
+            ctr.setdefault((inst, label, c), []).append(
+                float(r["Counter_Value"]) * 1024 * scales[c] / cells)
+
+    lines = [f"kernel source sha256[:16] = {kernel_source_hash()} (headline kernel sources)"]
+    if scales:
+        lines.append("counter scales (2 GiB device copy in the same pass): "
+                     + ", ".join(f"{c} {s:.4f}" for c, s in scales.items()))
+    lines.append("per launch: time from the trace; B/cell = algorithmic bytes per cell "
+                 "(each value read or written once), TB/s = algorithmic bytes / average time; "
+                 "rd, wr = counter bytes per cell, x = (rd + wr) / algorithmic")
+    lines.append("flags: k_step<STORE_MOM,HOLD,POP>, k_step_aa<PUSH,HOLD,STORE_MOM>, "
+                 "k_adjoint<COLLIDE,MARK,HOLD>; vgpr is rocprofv3's VGPR_Count (half the "
+                 "registers per lane on gfx950); k_stream_copy moves the headline state")
+    lines.append("")
+    lines.append(f"{'instance':34s} {'grid':>10s} {'wg':>4s} {'vgpr':>4s} {'n':>5s} "
+                 f"{'avg us':>10s} {'min us':>10s} {'B/cell':>7s} {'TB/s':>6s} {'of 8':>5s} "
+                 f"{'rd':>7s} {'wr':>7s} {'x':>6s}")
+    for (inst, label, wg, vgpr), g in groups.items():
+        n = len(g["ns"])
+        avg = sum(g["ns"]) / n
+        alg, cells = g["alg"], g["cells"]
+        rd = ctr.get((inst, label, "FETCH_SIZE"))
+        wr = ctr.get((inst, label, "WRITE_SIZE"))
+        if rd and wr:
+            rdv, wrv = sum(rd) / len(rd), sum(wr) / len(wr)
+            cnt = f"{rdv:7.1f} {wrv:7.1f} {(rdv + wrv) * cells / alg:6.3f}"
+        else:
+            cnt = f"{'-':>7s} {'-':>7s} {'-':>6s}"
+        lines.append(f"{inst:34s} {label:>10s} {wg:4d} {vgpr:4d} {n:5d} {avg / 1e3:10.2f} "
+                     f"{min(g['ns']) / 1e3:10.2f} {alg / cells:7.0f} {alg / avg / 1e3:6.2f} "
+                     f"{alg / avg / 8e3:5.2f} {cnt}")
+    lines.append("")
+    lines.append("other kernels (torch elementwise, reductions, runtime copies and fills, the "
+                 f"library's zero fills and partial sums): {other_ns / 1e6:.1f} ms in total")
+    return "\n".join(lines)
+
+
+def summarize_placement(prof_dir: str) -> str:
+    """Per-trial table of two rocprofv3 counter passes (lat/, tlb/) over
+    `bench.py --placement-trials`: the headline step's time, mean DRAM read
+    latency (TCC_EA0_RDREQ_LEVEL / TCC_EA0_RDREQ), address-translation misses
+    and the shader clock.  Trials are told apart by their k_init launches;
+    needs no GPU."""
+    import collections
+    out = ["trial  pass  step ms   read latency (cycles)  UTCL1 miss rate  UTCL2 busy  clock GHz"]
+    for sub in ("lat", "tlb"):
+        path = os.path.join(prof_dir, sub, f"{sub}_counter_collection.csv")
+        if not os.path.exists(path):
+            continue
+        disp = collections.OrderedDict()
+        for r in sorted(_read_counters(path), key=lambda r: int(r["Dispatch_Id"])):
+            d = disp.setdefault(int(r["Dispatch_Id"]), {
+                "name": r["Kernel_Name"], "grid": int(r["Grid_Size"]),
+                "ns": float(r["End_Timestamp"]) - float(r["Start_Timestamp"])})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+        trial, acc = -1, collections.OrderedDict()
+        for d in disp.values():
+            kernel, model, prec, _ = _instance(d["name"])
+            if d["grid"] != 384 ** 3 or model != "D3Q95" or prec != "F32S":
+                continue
+            if kernel == "k_init":
+                trial += 1
+            elif kernel == "k_step" and trial >= 0:
+                acc.setdefault(trial, []).append(d)
+        for t, ds in acc.items():
+            mean = lambda k: sum(x.get(k, 0.0) for x in ds) / len(ds)
+            ms = mean("ns") / 1e6
+            lat = (f"{mean('TCC_EA0_RDREQ_LEVEL_sum') / mean('TCC_EA0_RDREQ_sum'):21.0f}"
+                   if mean("TCC_EA0_RDREQ_sum") else f"{'-':>21s}")
+            if mean("TCP_UTCL1_REQUEST_sum"):
+                tlb = (f"{mean('TCP_UTCL1_TRANSLATION_MISS_sum') / mean('TCP_UTCL1_REQUEST_sum'):15.2e}"
+                       f"  {mean('GRBM_UTCL2_BUSY') / mean('GRBM_GUI_ACTIVE'):10.4f}"
+                       f"  {mean('GRBM_GUI_ACTIVE') / 8 / mean('ns'):9.3f}")
+            else:
+                tlb = f"{'-':>15s}  {'-':>10s}  {'-':>9s}"
+            out.append(f"{t:5d}  {sub:4s}  {ms:7.3f}  {lat}  {tlb}")
+    return "\n".join(out)
+
+
 SECTIONS = ("256c", "d2q33", "lower", "aa", "tubes", "adjoint")
 
 
@@ -489,13 +736,28 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 2 GiB device copy first (reference dispatch for HBM counters)")
+    ap.add_argument("--placement-trials", type=int, default=0,
+                    help="also time the headline step and the streaming copy on this many "
+                         "fresh allocations of the population buffers")
     ap.add_argument("--only", default="",
                     help="comma-separated side measurements to run (default: all of them): "
                          + ",".join(SECTIONS))
     ap.add_argument("--summarize-profiles", metavar="DIR", default="",
                     help="print the summary of rocprofv3 runs of the headline command in DIR "
                          "(kt/, fetch/, write/, l2/) and update the traffic record; no GPU")
+    ap.add_argument("--summarize-all-profiles", metavar="DIR", default="",
+                    help="print the per-kernel table of rocprofv3 runs of the full bench in DIR "
+                         "(kt/ kernel trace, fetch/ and write/ counter passes); no GPU")
+    ap.add_argument("--summarize-placement-profiles", metavar="DIR", default="",
+                    help="print the per-trial table of rocprofv3 counter passes (lat/, tlb/) "
+                         "over --placement-trials runs in DIR; no GPU")
     args = ap.parse_args()
+    if args.summarize_placement_profiles:
+        print(summarize_placement(args.summarize_placement_profiles))
+        return
+    if args.summarize_all_profiles:
+        print(summarize_all_kernels(args.summarize_all_profiles))
+        return
     if args.summarize_profiles:
         print(summarize_profiles(args.summarize_profiles, args.grid))
         return
@@ -568,6 +830,9 @@ def main():
     # the same bytes moved by a plain streaming copy on the same buffers
     out["roofline"]["copy_GBs"] = round(cbw, 1)
     out["roofline"]["frac_of_copy"] = round(achieved / cbw, 4)
+    if args.placement_trials > 0:
+        log(f"[bench] {args.placement_trials} placements of the headline buffers")
+        out["placement_384c"] = run_placement(extent, omega, args.placement_trials)
     if not args.no_extras and want("256c"):
         log("[bench] fp64 vs fp32s on 256^3")
         thr, errs = run_fp64_and_error((256, 256, 256), 1.5, 100, 200, steps_err_long=1000)
