@@ -434,9 +434,10 @@ int lbm_adjoint_workspace_bytes(const lbm_ctx* ctx, int n, int k, int keep, size
  *                        Accuracy: A - K nearly cancels and is divided by
  *                        1 - omega, so the LBM_FP32_SHIFTED error grows like
  *                        1/|1 - omega| (measured against central differences
- *                        of the float64 run, D3Q95 48x40x32, 60 steps:
- *                        3.4e-5 at omega = 0.9, 4.4e-4 at omega = 1.05; 128^3,
- *                        200 steps: 7e-6 at omega = 1.4).  LBM_FP64 stays near
+ *                        of the float64 run, D3Q95 48x40x32, 60 steps, over
+ *                        several runs: 3.4e-5 to 1.0e-4 at omega = 0.9,
+ *                        2.2e-4 to 4.4e-4 at omega = 1.05; 128^3, 200 steps:
+ *                        5e-6 to 7e-6 at omega = 1.4).  LBM_FP64 stays near
  *                        1e-12 relative.
  * With held planes (lbm_set_fixed_planes, set as in the forward run) the
  * post-collision values of held cells are constants: their adjoint state is
