@@ -8,7 +8,10 @@ step) after W warm-up steps.  Prints ONE JSON line with MLUPS, the roofline
 of the dominant kernel (algorithmic bytes 2 Q 4 = 760 B per cell update over
 the HIP-event duration of the timed launches, against 8 TB/s HBM; the HBM
 bytes per launch measured by rocprofv3 counters on the same kernel source),
-the CPU oracle's rate on a bounded sample, and side measurements: FP64 on
+the CPU oracle's rate on a bounded sample, the headline step and a plain
+copy of the same bytes on a few fresh allocations of its buffers (the step's
+speed depends on where in HBM they land; `value` is the first allocation's),
+and side measurements: FP64 on
 256^3, FP32-shifted vs FP64 error after 200 steps on 256^3, D2Q33 in both
 precisions on 8192^2, in-place (AA) streaming on 384^3 and on 768^3 (a grid
 whose two-buffer state would not fit in HBM), the two shock tubes with held
@@ -736,9 +739,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 2 GiB device copy first (reference dispatch for HBM counters)")
-    ap.add_argument("--placement-trials", type=int, default=0,
+    ap.add_argument("--placement-trials", type=int, default=None,
                     help="also time the headline step and the streaming copy on this many "
-                         "fresh allocations of the population buffers")
+                         "fresh allocations of the population buffers (default 4, or 0 with "
+                         "--no-extras)")
     ap.add_argument("--only", default="",
                     help="comma-separated side measurements to run (default: all of them): "
                          + ",".join(SECTIONS))
@@ -830,9 +834,11 @@ def main():
     # the same bytes moved by a plain streaming copy on the same buffers
     out["roofline"]["copy_GBs"] = round(cbw, 1)
     out["roofline"]["frac_of_copy"] = round(achieved / cbw, 4)
+    if args.placement_trials is None:
+        args.placement_trials = 0 if args.no_extras else 4
     if args.placement_trials > 0:
         log(f"[bench] {args.placement_trials} placements of the headline buffers")
-        out["placement_384c"] = run_placement(extent, omega, args.placement_trials)
+        out[f"placement_{args.grid}c"] = run_placement(extent, omega, args.placement_trials)
     if not args.no_extras and want("256c"):
         log("[bench] fp64 vs fp32s on 256^3")
         thr, errs = run_fp64_and_error((256, 256, 256), 1.5, 100, 200, steps_err_long=1000)
