@@ -52,8 +52,8 @@ struct lbm_ctx {
 
 namespace lbm {
 
-// Launch geometry (host only; the kernels' launch bounds are the same macros).
-int step_max_threads(Prec p) { return p == Prec::F64 ? LBM_F64_MAXB : LBM_STEP_MAXB; }
+// Launch geometry (host only; the kernels' launch bounds use the same limit).
+int step_max_threads(ModelId m, Prec p) { return row_block_limit(model_q(m), p); }
 
 RowLaunch row_launch(int nx, long long rows, int max_threads) {
     RowLaunch r;
@@ -165,14 +165,15 @@ void fill_kparams(lbm_ctx* ctx) {
     k.rg = 1 << k.rg_shift;
     k.N = ctx->N;
     const long long rows = static_cast<long long>(k.ny) * k.nz;
-    const lbm::RowLaunch rl = lbm::row_launch(k.nx, rows, lbm::step_max_threads(ctx->prec));
+    const lbm::RowLaunch rl =
+        lbm::row_launch(k.nx, rows, lbm::step_max_threads(ctx->model, ctx->prec));
     k.chunks = rl.chunks;
     k.bx = rl.bx;
     k.rpb = 1;
     if (lbm::kPackRows && k.nx % 64 == 0) {
         // whole rows per block: waves stay inside one row (nx % 64 = 0) and
         // no block is partly empty (rpb divides the row count)
-        const int maxb = std::min(lbm::step_max_threads(ctx->prec), lbm::kPackMaxBlock);
+        const int maxb = std::min(lbm::step_max_threads(ctx->model, ctx->prec), lbm::kPackMaxBlock);
         while (k.nx * k.rpb * 2 <= maxb && rows % (k.rpb * 2) == 0) k.rpb *= 2;
         if (k.rpb > 1) k.bx = k.nx * k.rpb;   // else: the row launch above (chunks >= 1)
     }
@@ -334,7 +335,7 @@ LBM_API int lbm_create(lbm_ctx** out, int D, int Q, const int32_t* e, const doub
     const long long rows = N / extent[0];
     const lbm::RowLaunch rl =
         lbm::row_launch(static_cast<int>(extent[0]), rows,
-                        lbm::step_max_threads(precision == LBM_FP64 ? Prec::F64 : Prec::F32S));
+                        lbm::step_max_threads(m, precision == LBM_FP64 ? Prec::F64 : Prec::F32S));
     if (rl.blocks >= (1LL << 31) || rl.blocks * rl.bx >= (1LL << 32))
         return fail(nullptr, LBM_E_INVALID, "grid too large for one launch");
     // The kernels address one slab of the slowest axis (all populations of a

@@ -1,5 +1,5 @@
 // lbm_internal.h - parameters and launchers shared by the C-ABI layer
-// (lbm_api.cpp) and the kernels (lbm_kernels.hip).  Not part of the public ABI.
+// (lbm_api.cpp) and the kernels (lbm_kernels.h).  Not part of the public ABI.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,8 +9,8 @@
 
 #include "lbm_model.h"
 
-// Largest block of the row-blocked kernels (launch bounds): float32 storage,
-// float64 storage.
+// Largest block of the row-blocked kernels (launch bounds): the default, and
+// float64 storage with the 4th-order sets.
 #ifndef LBM_STEP_MAXB
 #define LBM_STEP_MAXB 512
 #endif
@@ -19,6 +19,17 @@
 #endif
 
 namespace lbm {
+
+// Largest block of the row-blocked kernels (step, in-place step, adjoint)
+// for a set of Q velocities stored in precision p; the kernels' launch
+// bounds and the host's launch geometry both take it from here.  Float64
+// with Q >= 33 (up to 256 VGPRs per lane) keeps 256 threads; the lower-order
+// float64 sets and FP32-shifted take 512 (measured with both limits bound to
+// the same buffers: D3Q19 and D3Q15 float64 at 384^3 1.5-1.9 % faster with
+// 512, D3Q95 float64 0.1-0.8 % slower).
+constexpr int row_block_limit(int Q, Prec p) {
+    return (p == Prec::F64 && Q >= 33) ? LBM_F64_MAXB : LBM_STEP_MAXB;
+}
 
 // Elements added to every population run of a row (run stride = nx + pad).
 #ifndef LBM_RUN_PAD
@@ -112,8 +123,9 @@ struct RowLaunch {
 };
 
 RowLaunch row_launch(int nx, long long rows, int max_threads);
-// Largest block size the row-blocked kernels of a precision are compiled for.
-int step_max_threads(Prec p);
+// Largest block size the row-blocked kernels of a model and precision are
+// compiled for (row_block_limit of its Q).
+int step_max_threads(ModelId m, Prec p);
 
 // Number of blocks of the grid-stride reduction kernels.
 int reduce_blocks(long long N);

@@ -102,19 +102,18 @@ __device__ __forceinline__ void static_for(F&& f) {
     static_for_impl(static_cast<F&&>(f), std::make_integer_sequence<int, N>{});
 }
 
-// Largest block of the row-blocked kernels (step, adjoint) per precision:
-// float64 keeps 256 threads so that a wave may use up to 512 VGPRs.
+// Storage precisions (their block limits: row_block_limit).
 struct F64T {
     using S = double;
     using Acc = double;   // type of the per-cell moment sums
-    static constexpr int max_block = LBM_F64_MAXB;
+    static constexpr Prec id = Prec::F64;
     static constexpr bool shifted = false;
     static constexpr int waves = 1;
     static constexpr int adj_waves = 1;
 };
 struct F32ST {
     using S = float;
-    static constexpr int max_block = LBM_STEP_MAXB;
+    static constexpr Prec id = Prec::F32S;
     // Moment sums of the float32 deviations in float64: a float32 sum of 95
     // terms is off by a few ulps of sum |e|^2 |g|, the same in every node of
     // a uniform region, so without it such regions drift coherently.
@@ -324,12 +323,17 @@ __device__ __forceinline__ void store_pop(char* p, S val) {
 
 // Gather v_i = src_i(x - SIGN*e_i) with periodic wrap on every axis.
 // Order in which a gather issues its loads: the velocity order, or sorted
-// by source slab, then source row (LBM_ADJ_GATHER_SORTED, transposed gather).
-// The order changes no value, only the issue order.  Measured on D3Q95
-// FP32-shifted: the forward pull sorted lost 0.5 % at 384^3, so it keeps the
-// velocity order; the adjoint sorted needs ~180 VGPRs (2 waves per SIMD) and
-// in velocity order fits 3 waves, which is 2 % faster at 128^3 (the adjoint
-// of 200 steps with recomputation: 117.2 against 119.6 ms, interleaved).
+// by source slab, then source row.  The order changes no value, only the
+// issue order.  Measured with builds of both orders bound to the same
+// buffers: the forward pull sorted is faster in 3D (D3Q95 FP64 256^3 by
+// 2.2 %, FP32-shifted 128^3 to 384^3 by 0.2-0.5 %, D3Q19 by 0.2 %) and slower
+// in 2D (D2Q33 8192^2 by 0.2-0.5 %); the adjoint sorted needs ~180 VGPRs
+// (2 waves per SIMD) and in velocity order fits 3 waves, which is 2 % faster
+// at 128^3 (the adjoint of 200 steps with recomputation: 117.2 against
+// 119.6 ms).
+#ifndef LBM_FWD_GATHER_SORTED_3D
+#define LBM_FWD_GATHER_SORTED_3D 1
+#endif
 #ifndef LBM_ADJ_GATHER_SORTED
 #define LBM_ADJ_GATHER_SORTED 0
 #endif
@@ -363,7 +367,8 @@ template <class M, int SIGN, class S>
 __device__ __forceinline__ void gather(const S* __restrict__ src, const KParams& k, const Cell& cl,
                                        S (&v)[M::Q]) {
     const SlabAddr<M, S, const char> ad(reinterpret_cast<const char*>(src), k, cl);
-    constexpr bool sorted = SIGN < 0 && LBM_ADJ_GATHER_SORTED != 0;
+    constexpr bool sorted = SIGN < 0 ? LBM_ADJ_GATHER_SORTED != 0
+                                     : (M::D == 3 && LBM_FWD_GATHER_SORTED_3D != 0);
     static_for<M::Q>([&](auto I) {
         constexpr int i = LoadOrder<M, sorted>::order.v[decltype(I)::value];
         constexpr int ex = SIGN * M::table.e[i][0];
@@ -696,7 +701,7 @@ __device__ __forceinline__ void store_held_moments(const KParams& k, const Cell&
 // relaxed or stored (the last recomputed step of a checkpoint segment,
 // whose post-collision state the next snapshot already holds).
 template <class M, class P, bool STORE_MOM, bool HOLD, bool POP = true>
-__global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
+__global__ __launch_bounds__(row_block_limit(M::Q, P::id)) __attribute__((amdgpu_waves_per_eu(P::waves)))
 void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst, KParams k,
             typename P::S* __restrict__ mom) {
     using S = typename P::S;
@@ -758,7 +763,7 @@ void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ d
 // two-buffer step), so both schemes hold the same values.
 // STORE_MOM: also store the step's D+2 moments, as k_step<STORE_MOM> does.
 template <class M, class P, bool PUSH, bool HOLD, bool STORE_MOM>
-__global__ __launch_bounds__(P::max_block) __attribute__((amdgpu_waves_per_eu(P::waves)))
+__global__ __launch_bounds__(row_block_limit(M::Q, P::id)) __attribute__((amdgpu_waves_per_eu(P::waves)))
 void k_step_aa(typename P::S* f, KParams k, typename P::S* __restrict__ mom) {
     using S = typename P::S;
     constexpr int D = M::D;
@@ -1057,7 +1062,7 @@ __device__ __forceinline__ R eq_pd(R c0, R c1, R c2, R s) {
 // their adjoint state is zero (the cells are computed like the others and
 // their output replaced, keeping every wave on the same barriers).
 template <class M, class P, bool COLLIDE, bool MARK, bool HOLD>
-__global__ __launch_bounds__(P::max_block)
+__global__ __launch_bounds__(row_block_limit(M::Q, P::id))
 __attribute__((amdgpu_waves_per_eu(MARK ? (P::adj_waves < 2 ? P::adj_waves : 2) : P::adj_waves)))
 void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict__ ldst,
                const typename P::S* __restrict__ mom, KParams k, double* __restrict__ partA,
@@ -1255,8 +1260,6 @@ inline unsigned cell_blocks(long long N) {
     return static_cast<unsigned>((N + kBlock - 1) / kBlock);
 }
 
-static_assert(F64T::max_block == LBM_F64_MAXB && F32ST::max_block == LBM_STEP_MAXB,
-              "step_max_threads (host) and the kernels' launch bounds must agree");
 static_assert(kBlock == kReduceThreads, "reduce_blocks (host) assumes kBlock threads");
 
 // Calls f with std::integral_constant<int, kp.form>.
