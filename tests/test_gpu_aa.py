@@ -97,6 +97,8 @@ def test_in_place_matches_oracle_and_set_populations(model, extent):
     ("D3Q95", (300, 2, 24), 0, 5),    # one held end; two chunks per row, ragged tail
     ("D2Q33", (7, 33), 4, 4),
     ("D2Q33", (5, 28), 3, 0),
+    ("D3Q19", (6, 4, 12), 2, 3),      # lower-order sets: displacements of 1
+    ("D3Q15", (5, 3, 9), 1, 1),
 ])
 @pytest.mark.parametrize("precision", ["fp64", "fp32s"])
 def test_in_place_with_held_planes_equals_two_buffer_bitwise(model, extent, n_lo, n_hi,
@@ -156,6 +158,8 @@ def test_paper_tube_in_place_equals_two_buffer_bitwise(precision):
     ("D3Q95", (20, 10, 8), 10, 3, 99, "fp64", 1),    # starts in the pushed form
     ("D2Q33", (20, 12), 13, 4, 2, "fp32s", 1),
     ("D3Q95", (7, 5, 4), 3, 2, 1, "fp64", 2),
+    ("D3Q19", (12, 8, 6), 9, 3, 1, "fp32s", 1),
+    ("D3Q15", (10, 6, 5), 8, 4, 2, "fp64", 0),
 ])
 def test_in_place_checkpoints_and_adjoint_equal_two_buffer_bitwise(model, extent, n, k, keep,
                                                                    precision, pre):

@@ -23,7 +23,8 @@ def _equal(a, b):
     return all(torch.equal(x, y) for x, y in zip(a, b))
 
 
-@pytest.mark.parametrize("model,extent", [("D3Q95", (20, 10, 8)), ("D2Q33", (33, 17))])
+@pytest.mark.parametrize("model,extent", [("D3Q95", (20, 10, 8)), ("D2Q33", (33, 17)),
+                                          ("D3Q19", (14, 8, 6)), ("D3Q15", (9, 6, 5))])
 @pytest.mark.parametrize("precision", ["fp64", "fp32s"])
 @pytest.mark.parametrize("streaming", ["ab", "aa"])
 def test_resume_from_every_snapshot_is_bitwise(model, extent, precision, streaming):

@@ -32,7 +32,8 @@ def _check(a, b):
     assert torch.equal(a.get_populations(), b.get_populations())
 
 
-@pytest.mark.parametrize("model,extent", [("D3Q95", (12, 6, 5)), ("D2Q33", (40, 9))])
+@pytest.mark.parametrize("model,extent", [("D3Q95", (12, 6, 5)), ("D2Q33", (40, 9)),
+                                          ("D3Q19", (16, 6, 5))])
 @pytest.mark.parametrize("precision", ["fp64", "fp32s"])
 @pytest.mark.parametrize("streaming", ["ab", "aa"])
 def test_graph_replay_equals_single_launches(model, extent, precision, streaming):
