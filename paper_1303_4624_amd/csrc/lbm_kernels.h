@@ -51,42 +51,43 @@
 namespace lbm {
 namespace {
 
+// Build-time switches, each at its measured best (alternatives timed on the
+// same buffers unless noted):
+// non-temporal stores of the two-buffer steps (plain stores 4-8 % slower);
 #ifndef LBM_NT_STORE
 #define LBM_NT_STORE 1
 #endif
+// non-temporal loads (8 % slower);
 #ifndef LBM_NT_LOAD
 #define LBM_NT_LOAD 0
 #endif
+// each XCD takes a contiguous range of rows (round-robin 4-5 % slower);
 #ifndef LBM_XCD_REMAP
 #define LBM_XCD_REMAP 1
 #endif
-#ifndef LBM_ADJ_SCHED_BARRIER
-#define LBM_ADJ_SCHED_BARRIER 0
-#endif
-// Occupancy target of the FP32-shifted adjoint kernel (waves per SIMD): 3
+// occupancy target of the FP32-shifted adjoint kernel (waves per SIMD): 3
 // waves (<= 168 VGPRs) fit without scratch when its loads are issued in
 // velocity order (LBM_ADJ_GATHER_SORTED 0); sorted by source row they need
-// about 180 VGPRs, which fit 2 waves only.
+// about 180 VGPRs, which fit 2 waves only;
 #ifndef LBM_ADJ_WAVES
 #define LBM_ADJ_WAVES 3
 #endif
+// minimum waves per SIMD of the FP32-shifted steps (the compiler's budget;
+// they hold 125-172 VGPRs);
 #ifndef LBM_F32_WAVES
 #define LBM_F32_WAVES 1
 #endif
-// The pushed stores of the AA kernel start at x + e_x, off the 128-byte
-// line grid; plain stores let L2 merge the partial lines of neighbouring
-// waves before they reach HBM (measured 5 % faster than non-temporal).
-// Dynamic LDS reserved per block of the step kernels (limits blocks per CU).
-#ifndef LBM_STEP_DYN_LDS
-#define LBM_STEP_DYN_LDS 0
-#endif
+// the pushed stores of the AA kernel start at x + e_x, off the 128-byte line
+// grid; plain stores let L2 merge the partial lines of neighbouring waves
+// before they reach HBM (non-temporal 8 % slower); its own-row stores are
+// non-temporal like the two-buffer step's;
 #ifndef LBM_AA_NT_PUSH
 #define LBM_AA_NT_PUSH 0
 #endif
 #ifndef LBM_AA_NT_LOCAL
 #define LBM_AA_NT_LOCAL 1
 #endif
-
+// float64 moment sums of the FP32-shifted storage (see F32ST).
 #ifndef LBM_F32S_SUM64
 #define LBM_F32S_SUM64 1
 #endif
@@ -1149,9 +1150,6 @@ void k_adjoint(const typename P::S* __restrict__ lsrc, typename P::S* __restrict
             if constexpr (ey != 0) ty = fma(R(ey), t, ty);
             if constexpr (ez != 0) tz = fma(R(ez), t, tz);
         });
-#if LBM_ADJ_SCHED_BARRIER
-        __builtin_amdgcn_sched_barrier(0);
-#endif
         const double wg = k.W[g];
         if constexpr (MARK) {
             // sum_i mu_i B_i of the group: the stored part in storage precision,
@@ -1319,7 +1317,7 @@ hipError_t ModelKernels<M, PR>::step(const KParams& kp, const void* src, void* d
     using S = typename P::S;
     const dim3 grid(static_cast<unsigned>(step_blocks(M::id, PR, kp)));
     const auto go = [&](auto kernel) {
-        hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s,
+        hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), 0, s,
                            static_cast<const S*>(src), static_cast<S*>(dst), kp,
                            static_cast<S*>(mom_out));
     };
@@ -1344,7 +1342,7 @@ hipError_t ModelKernels<M, PR>::step_aa(const KParams& kp, void* f, bool push, v
     using S = typename P::S;
     const dim3 grid(static_cast<unsigned>(step_blocks(M::id, PR, kp)));
     const auto go = [&](auto kernel) {
-        hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), LBM_STEP_DYN_LDS, s, static_cast<S*>(f), kp,
+        hipLaunchKernelGGL(kernel, grid, dim3(kp.bx), 0, s, static_cast<S*>(f), kp,
                            static_cast<S*>(mom_out));
     };
     const bool hold = kp.hold_lo + kp.hold_hi > 0;
