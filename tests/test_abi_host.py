@@ -256,3 +256,27 @@ def test_graph_steps_validation():
             assert ex.value.status == want, steps
     finally:
         L.lbm_destroy(ctx)
+
+
+def test_plain_c_caller(tmp_path):
+    """The header is valid C99 (no C++ constructs leak out of extern "C"), and
+    a C program linked against liblbm.so gets the documented results from
+    the host-side calls (tests/c_abi/host_calls.c)."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    lib_dir = os.path.join(ROOT, "paper_1303_4624_amd")
+    if not os.path.exists(os.path.join(lib_dir, "liblbm.so")):
+        pytest.skip("liblbm.so is not built")
+    exe = str(tmp_path / "host_calls")
+    cmd = [cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+           "-I", os.path.join(ROOT, "include"),
+           os.path.join(ROOT, "tests", "c_abi", "host_calls.c"),
+           "-L", lib_dir, "-llbm", f"-Wl,-rpath,{lib_dir}", "-lm", "-o", exe]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    run = subprocess.run([exe], capture_output=True, text=True, timeout=120)
+    assert run.returncode == 0, run.stdout + run.stderr
+    assert "all host-side checks passed" in run.stdout
