@@ -64,8 +64,15 @@ def measured_traffic():
 
 
 def timed_steps(sim, steps, warmup):
+    """Wall and event seconds of `steps` steps after `warmup` untimed ones;
+    with two buffers the warm-up steps also pick the faster block order of
+    the forward step on these buffers (Simulation.tune_step, bit-identical
+    to plain steps)."""
     import torch
-    sim.step(warmup)
+    if sim.streaming == "ab" and warmup >= 4:
+        sim.tune_step(warmup)
+    else:
+        sim.step(warmup)
     torch.cuda.synchronize()
     stream = sim.stream            # the stream the library launches on
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -90,6 +97,7 @@ def run_headline(extent, omega, steps, warmup):
     sim.init_fields(rho, U, th * sim.T0)
     del rho, U, th
     wall, ev = timed_steps(sim, steps, warmup)
+    order = sim.block_order
     r, _, _ = sim.moments()
     ok = bool(torch.isfinite(r).all())
     cons = sim.conservation()
@@ -97,7 +105,7 @@ def run_headline(extent, omega, steps, warmup):
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return wall, ev, ok, cons, copy_gbs
+    return wall, ev, ok, cons, copy_gbs, order
 
 
 def run_placement(extent, omega, trials, steps=20):
@@ -119,11 +127,12 @@ def run_placement(extent, omega, trials, steps=20):
         gbs = copy_bandwidth(sim)
         step_ms = ev / steps * 1e3
         copy_ms = 2 * sim.pop_bytes / gbs / 1e6
+        order = sim.block_order
         sim.close()
         del sim, spacer
         torch.cuda.empty_cache()
         out.append({"step_ms": round(step_ms, 4), "copy_ms": round(copy_ms, 4),
-                    "step_over_copy": round(step_ms / copy_ms, 4)})
+                    "step_over_copy": round(step_ms / copy_ms, 4), "block_order": order})
         log(f"[bench] placement trial {t}: step {step_ms:.3f} ms, copy {copy_ms:.3f} ms")
     return out
 
@@ -422,22 +431,36 @@ def _read_counters(path):
         return list(csv.DictReader(fh))
 
 
-def summarize_profiles(prof_dir: str, grid: int = 384) -> str:
+def _timed_dispatches(rows, name, steps):
+    """The last `steps` dispatches of kernel `name` in dispatch order (the
+    headline's timed steps come after its warm-up steps); `steps` <= 0: all."""
+    sel = sorted((r for r in rows if _instance(r["Kernel_Name"])[0] == name),
+                 key=lambda r: int(r["Dispatch_Id"]))
+    return sel[-steps:] if steps > 0 else sel
+
+
+def summarize_profiles(prof_dir: str, grid: int = 384, steps: int = 0) -> str:
     """Text summary of the rocprofv3 runs of the headline command (kernel
-    stats, FETCH_SIZE and WRITE_SIZE passes, an L2 pass) under prof_dir;
-    also writes the traffic record the bench reads (TRAFFIC_FILE) when the
-    counter passes are present.  Needs no GPU."""
+    trace, FETCH_SIZE and WRITE_SIZE passes, an L2 pass) under prof_dir: the
+    step kernel over the last `steps` launches (the timed region, after the
+    warm-up steps), the streaming copy over all of its launches.  Also writes
+    the traffic record the bench reads (TRAFFIC_FILE) when the counter passes
+    are present.  Needs no GPU."""
     import csv
     N = grid ** 3
     alg = 2 * 95 * 4 * N
     lines = []
-    stats = os.path.join(prof_dir, "kt", "kt_kernel_stats.csv")
+    trace = os.path.join(prof_dir, "kt", "kt_kernel_trace.csv")
     avg = {}
-    if os.path.exists(stats):
-        with open(stats) as fh:
-            for r in csv.DictReader(fh):
-                avg[r["Name"]] = (int(r["Calls"]), float(r["AverageNs"]), float(r["MinNs"]))
-        lines.append("kernel statistics (rocprofv3 --kernel-trace --stats):")
+    if os.path.exists(trace):
+        with open(trace) as fh:
+            rows = list(csv.DictReader(fh))
+        for name, last in (("k_step", steps), ("k_stream_copy", 0)):
+            d = [float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+                 for r in _timed_dispatches(rows, name, last)]
+            if d:
+                avg[name] = (len(d), sum(d) / len(d), min(d))
+        lines.append("kernel trace (rocprofv3 --kernel-trace; k_step: the timed launches):")
         for name in ("k_step", "k_stream_copy"):
             if name in avg:
                 calls, a, mn = avg[name]
@@ -460,8 +483,8 @@ def summarize_profiles(prof_dir: str, grid: int = 384) -> str:
         if not cal:
             continue
         scales[ctr] = (1 << 31) / (cal[0] * 1024)
-        for name in ("k_step", "k_stream_copy"):
-            v = [float(r["Counter_Value"]) for r in rows if r["Kernel_Name"] == name]
+        for name, last in (("k_step", steps), ("k_stream_copy", 0)):
+            v = [float(r["Counter_Value"]) for r in _timed_dispatches(rows, name, last)]
             if v:
                 per[(name, ctr)] = (len(v), sum(v) / len(v) * 1024 * scales[ctr])
     if scales:
@@ -490,14 +513,16 @@ def summarize_profiles(prof_dir: str, grid: int = 384) -> str:
                 json.dump(rec, fh, indent=1)
     l2 = os.path.join(prof_dir, "l2", "l2_counter_collection.csv")
     if os.path.exists(l2):
-        rows = [r for r in _read_counters(l2) if r["Kernel_Name"] in ("k_step", "k_stream_copy")]
+        rows = _read_counters(l2)
         lines.append("")
         lines.append("L2 (TCC) counters per cell update, mean over launches:")
-        for name in ("k_step", "k_stream_copy"):
+        for name, last in (("k_step", steps), ("k_stream_copy", 0)):
             tot = {}
-            for r in rows:
-                if r["Kernel_Name"] == name:
-                    tot.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            cnames = sorted(set(r["Counter_Name"] for r in rows))
+            for c in cnames:
+                sel = [r for r in rows if r["Counter_Name"] == c]
+                for r in _timed_dispatches(sel, name, last):
+                    tot.setdefault(c, []).append(float(r["Counter_Value"]))
             if tot:
                 txt = ", ".join(f"{c} {sum(v) / len(v) / N:.3f}" for c, v in sorted(tot.items()))
                 lines.append(f"  {name:14s} {txt}")
@@ -763,7 +788,7 @@ def main():
         print(summarize_all_kernels(args.summarize_all_profiles))
         return
     if args.summarize_profiles:
-        print(summarize_profiles(args.summarize_profiles, args.grid))
+        print(summarize_profiles(args.summarize_profiles, args.grid, args.steps))
         return
     only = set(x for x in args.only.split(",") if x)
     if only - set(SECTIONS):
@@ -796,7 +821,7 @@ def main():
     omega = 1.8
     Q = 95
     log(f"[bench] headline D3Q95 fp32s {extent}, {args.steps} steps")
-    wall, ev, ok, cons, cbw = run_headline(extent, omega, args.steps, args.warmup)
+    wall, ev, ok, cons, cbw, order = run_headline(extent, omega, args.steps, args.warmup)
     N = args.grid ** 3
     mlups = N * args.steps / ev / 1e6
     per_launch_s = ev / args.steps
@@ -830,6 +855,9 @@ def main():
                                                   if traffic else None)},
         "finite": ok,
         "mass_after": cons[0],
+        # block order of the forward step kept by the warm-up steps (0:
+        # contiguous rows per XCD, 1: z-planes in turn)
+        "block_order": order,
     }
     # the same bytes moved by a plain streaming copy on the same buffers
     out["roofline"]["copy_GBs"] = round(cbw, 1)

@@ -31,7 +31,7 @@ LBM_MAX_Q = 95
 
 EXPORTED = [
     "lbm_velocity_set", "lbm_equation_count", "lbm_model_build", "lbm_create", "lbm_workspace_bytes", "lbm_bind", "lbm_init_fields",
-    "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_moments",
+    "lbm_set_populations", "lbm_get_populations", "lbm_step", "lbm_tune_step", "lbm_set_block_order", "lbm_moments",
     "lbm_conservation", "lbm_conservation_noalloc", "lbm_stream_copy", "lbm_set_fixed_planes", "lbm_set_streaming", "lbm_set_graph_steps",
     "lbm_set_omega", "lbm_checkpoint_bytes", "lbm_run_checkpointed", "lbm_restore_checkpoint",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint", "lbm_destroy", "lbm_status_str",
@@ -67,6 +67,8 @@ _SIGS = {
     "lbm_set_populations": (_c.c_int, [_vp, _vp]),
     "lbm_get_populations": (_c.c_int, [_vp, _vp]),
     "lbm_step": (_c.c_int, [_vp, _c.c_int]),
+    "lbm_tune_step": (_c.c_int, [_vp, _c.c_int, _c.POINTER(_c.c_int)]),
+    "lbm_set_block_order": (_c.c_int, [_vp, _c.c_int]),
     "lbm_moments": (_c.c_int, [_vp, _vp, _vp, _vp]),
     "lbm_conservation": (_c.c_int, [_vp, _pd]),
     "lbm_conservation_noalloc": (_c.c_int, [_vp, _pd]),
@@ -212,6 +214,18 @@ def lbm_get_populations(ctx, f) -> None:
 
 def lbm_step(ctx, n: int) -> None:
     _check(library().lbm_step(ctx, int(n)), "lbm_step", ctx)
+
+
+def lbm_tune_step(ctx, n: int) -> int:
+    """lbm_step(n) that times the two block orders of the forward step on
+    the way and keeps the faster; returns the order kept (0 or 1)."""
+    m = _c.c_int(0)
+    _check(library().lbm_tune_step(ctx, int(n), _c.byref(m)), "lbm_tune_step", ctx)
+    return m.value
+
+
+def lbm_set_block_order(ctx, order: int) -> None:
+    _check(library().lbm_set_block_order(ctx, int(order)), "lbm_set_block_order", ctx)
 
 
 def lbm_moments(ctx, rho=None, U=None, T=None) -> None:

@@ -46,6 +46,8 @@ struct lbm_ctx {
     hipGraphExec_t graph_exec = nullptr;
     int graph_cur = -1, graph_form = -1;
     int hold_lo = 0, hold_hi = 0;   // planes held at f^eq at each end of the slowest axis
+    int mapping = 0;                // forward steps' block order: 0 contiguous rows per XCD,
+                                    // 1 slabs in turn (lbm_tune_step)
     lbm::FixedState hold[2]{};
     std::string err;
 };
@@ -153,6 +155,13 @@ int check_dev(lbm_ctx* ctx, const void* p, size_t bytes, const char* name) {
 // Storage form the state starts in after lbm_init_fields / lbm_set_populations.
 int initial_form(const lbm_ctx* ctx) { return ctx->aa ? lbm::kFormSwapped : lbm::kFormAB; }
 
+// Blocks of the forward step per slab of the slowest axis (a z-plane in 3D,
+// a row in 2D): the chunk the XCDs take in turn in the alternative mapping.
+int cyclic_chunk(const KParams& k, int D) {
+    const long long blocks = (D == 3 ? static_cast<long long>(k.ny) : 1LL) * k.chunks / k.rpb;
+    return static_cast<int>(std::max(1LL, std::min(blocks, 1LL << 20)));
+}
+
 void fill_kparams(lbm_ctx* ctx) {
     KParams& k = ctx->kp;
     if (!ctx->initialized) k.form = initial_form(ctx);
@@ -177,6 +186,7 @@ void fill_kparams(lbm_ctx* ctx) {
         while (k.nx * k.rpb * 2 <= maxb && rows % (k.rpb * 2) == 0) k.rpb *= 2;
         if (k.rpb > 1) k.bx = k.nx * k.rpb;   // else: the row launch above (chunks >= 1)
     }
+    k.xcd_cyclic = ctx->mapping ? cyclic_chunk(k, ctx->D) : 0;
     k.omega = ctx->omega;
     k.omc = 1.0 - ctx->omega;
     if (ctx->prec == Prec::F32S) k.omc = static_cast<double>(static_cast<float>(k.omc));
@@ -465,6 +475,8 @@ LBM_API int lbm_bind(lbm_ctx* ctx, void* f_a, void* f_b, void* scratch) {
     ctx->bound = true;
     ctx->initialized = false;
     ctx->kp.form = initial_form(ctx);
+    ctx->mapping = 0;   // a tuned block order belongs to the buffers it was measured on
+    ctx->kp.xcd_cyclic = 0;
     drop_graph(ctx);
     ctx->err.clear();
     return LBM_OK;
@@ -538,6 +550,72 @@ LBM_API int lbm_step(lbm_ctx* ctx, int n) {
         hipError_t e = launch_one_step(ctx);
         if (e != hipSuccess) return fail_hip(ctx, e, ctx->aa ? "in-place step kernel" : "step kernel");
     }
+    return LBM_OK;
+}
+
+LBM_API int lbm_tune_step(lbm_ctx* ctx, int n, int* mapping) {
+    int rc;
+    if ((rc = require_init(ctx)) != LBM_OK) return rc;
+    if (n < 0) return fail(ctx, LBM_E_INVALID, "n must be >= 0");
+    if ((rc = set_device(ctx)) != LBM_OK) return rc;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (ctx->stream) {
+        const hipError_t e = hipStreamIsCapturing(ctx->stream, &cap);
+        if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamIsCapturing");
+    }
+    constexpr int kTuneMinSteps = 4;
+    if (ctx->aa || n < kTuneMinSteps || cap != hipStreamCaptureStatusNone) {
+        if ((rc = lbm_step(ctx, n)) != LBM_OK) return rc;
+        if (mapping) *mapping = ctx->mapping;
+        return LBM_OK;
+    }
+    // n single steps, the two block orders alternating, each between two events
+    std::vector<hipEvent_t> ev(static_cast<size_t>(n) + 1, nullptr);
+    const auto release = [&]() {
+        for (hipEvent_t x : ev)
+            if (x) (void)hipEventDestroy(x);
+    };
+    hipError_t e = hipSuccess;
+    for (size_t t = 0; t < ev.size() && e == hipSuccess; ++t) e = hipEventCreate(&ev[t]);
+    if (e != hipSuccess) {
+        release();
+        return fail_hip(ctx, e, "hipEventCreate");
+    }
+    drop_graph(ctx);
+    const int chunk = cyclic_chunk(ctx->kp, ctx->D);
+    e = hipEventRecord(ev[0], ctx->stream);
+    for (int t = 0; t < n && e == hipSuccess; ++t) {
+        ctx->kp.xcd_cyclic = (t % 2) ? chunk : 0;
+        e = launch_one_step(ctx);
+        if (e == hipSuccess) e = hipEventRecord(ev[t + 1], ctx->stream);
+    }
+    if (e == hipSuccess) e = hipEventSynchronize(ev[n]);
+    // mean time of each order, leaving out the first step of each as warm-up
+    double sum[2] = {0.0, 0.0};
+    int cnt[2] = {0, 0};
+    for (int t = (n >= 6 ? 2 : 0); t < n && e == hipSuccess; ++t) {
+        float ms = 0.0f;
+        e = hipEventElapsedTime(&ms, ev[t], ev[t + 1]);
+        sum[t % 2] += ms;
+        ++cnt[t % 2];
+    }
+    release();
+    if (e != hipSuccess) {
+        ctx->kp.xcd_cyclic = ctx->mapping ? chunk : 0;
+        return fail_hip(ctx, e, "tuning steps");
+    }
+    ctx->mapping = (sum[1] * cnt[0] < sum[0] * cnt[1]) ? 1 : 0;
+    ctx->kp.xcd_cyclic = ctx->mapping ? chunk : 0;
+    if (mapping) *mapping = ctx->mapping;
+    return LBM_OK;
+}
+
+LBM_API int lbm_set_block_order(lbm_ctx* ctx, int order) {
+    if (!ctx) return fail(nullptr, LBM_E_INVALID, "context is NULL");
+    if (order != 0 && order != 1) return fail(ctx, LBM_E_INVALID, "order must be 0 or 1");
+    drop_graph(ctx);
+    ctx->mapping = order;
+    ctx->kp.xcd_cyclic = order ? cyclic_chunk(ctx->kp, ctx->D) : 0;
     return LBM_OK;
 }
 

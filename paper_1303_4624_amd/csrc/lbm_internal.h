@@ -101,6 +101,8 @@ struct KParams {
     int chunks;               // blocks per grid row (x direction)
     int rpb;                  // grid rows per block (> 1 only with chunks = 1, nx % 64 = 0)
     int bx;                   // threads per block (multiple of 64)
+    int xcd_cyclic;           // > 0: the forward steps hand the 8 XCDs chunks of this
+                              // many blocks in turn; 0: a contiguous range each
     long long N;              // cells
     double omega;             // relaxation frequency
     double omc;               // 1 - omega as used by the kernels (float-rounded for F32S)

@@ -232,14 +232,27 @@ struct PopAt<M, kFormPushed> {
 
 // Row-blocked mapping: block b covers threads [chunk*bx, chunk*bx + bx) of
 // grid row `row` = y + ny*z.  y and z are uniform over the block.
+// Blocks are dispatched round-robin over the 8 XCDs.  By default each XCD
+// takes a contiguous range of rows, so the chunks of a row share one L2.
+// CYCLIC (the forward steps, which sum nothing across blocks, so the mapping
+// cannot change a result): with k.xcd_cyclic > 0 and a grid of a multiple of
+// 8 * xcd_cyclic blocks, the XCDs take chunks of xcd_cyclic blocks in turn
+// instead.  Which of the two is faster depends on where the buffers lie in
+// HBM (lbm_tune_step measures it).
+template <bool CYCLIC = false>
 __device__ __forceinline__ Cell row_cell(const KParams& k) {
 #if LBM_XCD_REMAP
-    // Blocks are dispatched round-robin over the 8 XCDs; give each XCD a
-    // contiguous range of rows so the chunks of a row share one L2.
     const int hb = blockIdx.x;
     const int nb = gridDim.x;
-    const int xcd = hb & 7, pos = hb >> 3, q = nb >> 3, r = nb & 7;
-    const int b = (xcd < r) ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+    const int xcd = hb & 7, pos = hb >> 3;
+    const int cc = CYCLIC ? k.xcd_cyclic : 0;
+    int b;
+    if (cc > 0 && nb % (8 * cc) == 0) {
+        b = ((pos / cc) * 8 + xcd) * cc + pos % cc;
+    } else {
+        const int q = nb >> 3, r = nb & 7;
+        b = (xcd < r) ? xcd * (q + 1) + pos : r * (q + 1) + (xcd - r) * q + pos;
+    }
 #else
     const int b = blockIdx.x;
 #endif
@@ -708,7 +721,7 @@ void k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ d
     using S = typename P::S;
     constexpr int D = M::D;
     static_assert(POP || STORE_MOM, "a step stores populations, moments or both");
-    const Cell cl = row_cell(k);
+    const Cell cl = row_cell<true>(k);
 
     if constexpr (HOLD) {
         const int sl = (D == 3) ? cl.z : cl.y;

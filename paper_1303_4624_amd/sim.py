@@ -68,6 +68,7 @@ class Simulation:
         self._scratch = _dev_bytes(scr, self.device)
         with torch.cuda.device(self.device):
             L.lbm_bind(self.ctx, self._fa, self._fb, self._scratch)
+        self.block_order = 0
 
     # -- shapes --------------------------------------------------------
     @property
@@ -117,6 +118,20 @@ class Simulation:
 
     def step(self, n: int = 1) -> None:
         self._call(L.lbm_step, self.ctx, n)
+
+    def tune_step(self, n: int) -> int:
+        """step(n), bit for bit, timing on the way the two block orders of
+        the forward step on these buffers and keeping the faster; returns
+        the order kept (0: contiguous rows per XCD, 1: slabs in turn).
+        Synchronises the library's stream when it tunes (n >= 4, two-buffer
+        streaming)."""
+        self.block_order = self._call(L.lbm_tune_step, self.ctx, n)
+        return self.block_order
+
+    def set_block_order(self, order: int) -> None:
+        """Set the forward steps' block order (0 or 1) without timing."""
+        L.lbm_set_block_order(self.ctx, order)
+        self.block_order = order
 
     def moments(self):
         rho = torch.empty(self.grid_shape, dtype=torch.float64, device=self.device)
