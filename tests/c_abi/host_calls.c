@@ -63,6 +63,13 @@ int main(void) {
             check(lbm_checkpoint_bytes(ctx, 20, 5, 1, &ck) == LBM_OK && ck > 4 * pop,
                   "checkpoint bytes hold the snapshots");
             check(lbm_step(ctx, 1) == LBM_E_STATE, "lbm_step before lbm_bind is refused");
+            {
+                int order = -1;
+                check(lbm_tune_step(ctx, 8, &order) == LBM_E_STATE && order == -1,
+                      "lbm_tune_step before lbm_bind is refused");
+                check(lbm_set_block_order(ctx, 1) == LBM_OK, "lbm_set_block_order 1");
+                check(lbm_set_block_order(ctx, 2) == LBM_E_INVALID, "block order 2 is refused");
+            }
             check(strlen(lbm_last_error(ctx)) > 0, "the refusal is explained");
             check(lbm_destroy(ctx) == LBM_OK, "lbm_destroy");
         }
