@@ -265,24 +265,26 @@ int lbm_step(lbm_ctx* ctx, int n);
  * the forward steps hand out their blocks, and keeping the faster order for
  * the steps that follow.
  *
- * The blocks of a two-buffer step are dispatched round-robin over the 8
- * XCDs of the device.  Order 0 (the default) gives each XCD a contiguous
+ * The blocks of a forward step (two-buffer or in place) are dispatched
+ * round-robin over the 8 XCDs of the device.  Order 0 (the default) gives each XCD a contiguous
  * range of rows; order 1 gives the XCDs one slab of the slowest axis (a
  * z-plane in 3D, a row in 2D) in turn.  Which is faster depends on where in
  * HBM the bound buffers lie (measured on D3Q95 FP32-shifted 384^3: order 1
- * 0.4-1.3 % faster on some placements, 1.5-2 % slower on others).  The
+ * 0.4-1.3 % faster on some placements, 1.5-2 % slower on others; in place
+ * 0.5 % faster on the placements measured).  The
  * order only decides which blocks run where: every step, the checkpointed
  * forward run and the recomputation in lbm_adjoint give bit-identical
  * results under both, and the kernels that sum across blocks (conservation,
  * adjoint) keep order 0, so their rounding does not depend on it.
  *
  *   n       : steps to run (>= 0); the result equals lbm_step(ctx, n) bit
- *             for bit.  The steps alternate the two orders, each between
- *             two events on the context's stream; the first step of each
- *             order counts as warm-up when n >= 6.
+ *             for bit.  The steps alternate the two orders (in place: per
+ *             pair of steps, one of each kernel), each step between two
+ *             events on the context's stream; the first step (pair) of each
+ *             order counts as warm-up when n >= 6 (in place 12).
  *   mapping : host int out (may be NULL), the order kept: 0 or 1.
- * Tuning needs n >= 4, the two-buffer scheme and a stream that is not being
- * captured; otherwise this is lbm_step(ctx, n) and the order stays.  The
+ * Tuning needs n >= 4 (in place 8) and a stream that is not being captured;
+ * otherwise this is lbm_step(ctx, n) and the order stays.  The
  * call synchronises the stream when it tunes.  lbm_bind resets the order
  * to 0.  Errors as lbm_step.
  */

@@ -563,13 +563,16 @@ LBM_API int lbm_tune_step(lbm_ctx* ctx, int n, int* mapping) {
         const hipError_t e = hipStreamIsCapturing(ctx->stream, &cap);
         if (e != hipSuccess) return fail_hip(ctx, e, "hipStreamIsCapturing");
     }
-    constexpr int kTuneMinSteps = 4;
-    if (ctx->aa || n < kTuneMinSteps || cap != hipStreamCaptureStatusNone) {
+    // In place the steps alternate between two kernels (push, local), so the
+    // orders alternate per pair of steps there.
+    const int unit = ctx->aa ? 2 : 1;
+    if (n < 4 * unit || cap != hipStreamCaptureStatusNone) {
         if ((rc = lbm_step(ctx, n)) != LBM_OK) return rc;
         if (mapping) *mapping = ctx->mapping;
         return LBM_OK;
     }
-    // n single steps, the two block orders alternating, each between two events
+    // n single steps, the two block orders alternating (per step, or per pair
+    // in place), each step between two events
     std::vector<hipEvent_t> ev(static_cast<size_t>(n) + 1, nullptr);
     const auto release = [&]() {
         for (hipEvent_t x : ev)
@@ -585,26 +588,27 @@ LBM_API int lbm_tune_step(lbm_ctx* ctx, int n, int* mapping) {
     const int chunk = cyclic_chunk(ctx->kp, ctx->D);
     e = hipEventRecord(ev[0], ctx->stream);
     for (int t = 0; t < n && e == hipSuccess; ++t) {
-        ctx->kp.xcd_cyclic = (t % 2) ? chunk : 0;
+        ctx->kp.xcd_cyclic = ((t / unit) % 2) ? chunk : 0;
         e = launch_one_step(ctx);
         if (e == hipSuccess) e = hipEventRecord(ev[t + 1], ctx->stream);
     }
     if (e == hipSuccess) e = hipEventSynchronize(ev[n]);
-    // mean time of each order, leaving out the first step of each as warm-up
+    // mean time of each order, leaving out the first step (pair) of each as
+    // warm-up when there are enough
     double sum[2] = {0.0, 0.0};
     int cnt[2] = {0, 0};
-    for (int t = (n >= 6 ? 2 : 0); t < n && e == hipSuccess; ++t) {
+    for (int t = (n >= 6 * unit ? 2 * unit : 0); t < n && e == hipSuccess; ++t) {
         float ms = 0.0f;
         e = hipEventElapsedTime(&ms, ev[t], ev[t + 1]);
-        sum[t % 2] += ms;
-        ++cnt[t % 2];
+        sum[(t / unit) % 2] += ms;
+        ++cnt[(t / unit) % 2];
     }
     release();
     if (e != hipSuccess) {
         ctx->kp.xcd_cyclic = ctx->mapping ? chunk : 0;
         return fail_hip(ctx, e, "tuning steps");
     }
-    ctx->mapping = (sum[1] * cnt[0] < sum[0] * cnt[1]) ? 1 : 0;
+    if (cnt[0] > 0 && cnt[1] > 0) ctx->mapping = (sum[1] * cnt[0] < sum[0] * cnt[1]) ? 1 : 0;
     ctx->kp.xcd_cyclic = ctx->mapping ? chunk : 0;
     if (mapping) *mapping = ctx->mapping;
     return LBM_OK;

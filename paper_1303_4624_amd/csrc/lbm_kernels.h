@@ -781,7 +781,7 @@ __global__ __launch_bounds__(row_block_limit(M::Q, P::id)) __attribute__((amdgpu
 void k_step_aa(typename P::S* f, KParams k, typename P::S* __restrict__ mom) {
     using S = typename P::S;
     constexpr int D = M::D;
-    const Cell cl = row_cell(k);
+    const Cell cl = row_cell<true>(k);
     const SlabAddr<M, S, char> ad(reinterpret_cast<char*>(f), k, cl);
     const auto put = [&](auto I, S val) {
         constexpr int i = decltype(I)::value;

@@ -97,16 +97,31 @@ def test_checkpoints_adjoint_and_graphs_under_the_other_order(model, extent, pre
     torch.cuda.synchronize()
 
 
-def test_in_place_and_short_runs_do_not_tune():
-    model, extent = "D3Q95", (70, 24, 16)
-    a, b, _ = _pair(model, extent, "fp32s", streaming="aa")
+@pytest.mark.parametrize("model,extent,precision", [CASES[0], CASES[2]])
+def test_in_place_tuned_steps_equal_plain_steps(model, extent, precision):
+    _say("case", model, extent, precision)
+    a, b, _ = _pair(model, extent, precision, streaming="aa")
     try:
-        assert a.tune_step(8) == 0       # in place: plain steps
-        b.step(8)
+        order = a.tune_step(13)          # pairs of (push, local) steps, and one more
+        b.step(13)
+        _say("order kept", order)
+        assert order in (0, 1)
+        assert torch.equal(_state(a), _state(b))
+        for order in (1, 0):
+            a.set_block_order(order)
+            a.step(3)
+            b.step(3)
+            assert torch.equal(_state(a), _state(b)), order
+        assert a.tune_step(7) == order   # in place: fewer than 8 steps do not tune
+        b.step(7)
         assert torch.equal(_state(a), _state(b))
     finally:
         a.close()
         b.close()
+
+
+def test_short_runs_do_not_tune():
+    model, extent = "D3Q95", (70, 24, 16)
     a, b, _ = _pair(model, extent, "fp32s")
     try:
         a.set_block_order(1)
